@@ -1,0 +1,76 @@
+"""Seeded value noise and fractional Brownian motion (fBm).
+
+Lattice values are uniform in [-1, 1) from the SplitMix64 hash of
+(lattice coordinates, octave, seed); they are blended with smoothstep
+weights (bi- or tri-linear).  Octave ``o`` has period ``P0 / 2**o`` and
+amplitude ``2**-o``; the sum is divided by the total amplitude so the result
+stays in [-1, 1].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .hashing import hash_keys, to_signed_unit
+
+
+def _smooth(f):
+    return f * f * (3.0 - 2.0 * f)
+
+
+def value_noise2(x, z, period: float, octave: int, seed: int):
+    u = np.asarray(x, dtype=np.float64) / period
+    v = np.asarray(z, dtype=np.float64) / period
+    i0 = np.floor(u)
+    k0 = np.floor(v)
+    fu = _smooth(u - i0)
+    fv = _smooth(v - k0)
+    i0 = i0.astype(np.int64)
+    k0 = k0.astype(np.int64)
+
+    def lat(di, dk):
+        return to_signed_unit(hash_keys(i0 + di, k0 + dk, octave, seed, 2))
+
+    a = lat(0, 0) * (1 - fu) + lat(1, 0) * fu
+    b = lat(0, 1) * (1 - fu) + lat(1, 1) * fu
+    return a * (1 - fv) + b * fv
+
+
+def value_noise3(x, y, z, period: float, octave: int, seed: int):
+    u = np.asarray(x, dtype=np.float64) / period
+    v = np.asarray(y, dtype=np.float64) / period
+    w = np.asarray(z, dtype=np.float64) / period
+    i0, j0, k0 = np.floor(u), np.floor(v), np.floor(w)
+    fu, fv, fw = _smooth(u - i0), _smooth(v - j0), _smooth(w - k0)
+    i0, j0, k0 = i0.astype(np.int64), j0.astype(np.int64), k0.astype(np.int64)
+
+    def lat(di, dj, dk):
+        return to_signed_unit(hash_keys(i0 + di, j0 + dj, k0 + dk, octave, seed, 3))
+
+    c00 = lat(0, 0, 0) * (1 - fu) + lat(1, 0, 0) * fu
+    c10 = lat(0, 1, 0) * (1 - fu) + lat(1, 1, 0) * fu
+    c01 = lat(0, 0, 1) * (1 - fu) + lat(1, 0, 1) * fu
+    c11 = lat(0, 1, 1) * (1 - fu) + lat(1, 1, 1) * fu
+    c0 = c00 * (1 - fv) + c10 * fv
+    c1 = c01 * (1 - fv) + c11 * fv
+    return c0 * (1 - fw) + c1 * fw
+
+
+def fbm2(x, z, octaves: int, period0: float, seed: int):
+    total = np.zeros(np.broadcast(np.asarray(x), np.asarray(z)).shape)
+    amp_sum = 0.0
+    for o in range(octaves):
+        amp = 2.0 ** -o
+        total = total + amp * value_noise2(x, z, period0 / 2.0 ** o, o, seed)
+        amp_sum += amp
+    return total / amp_sum
+
+
+def fbm3(x, y, z, octaves: int, period0: float, seed: int):
+    shape = np.broadcast(np.asarray(x), np.asarray(y), np.asarray(z)).shape
+    total = np.zeros(shape)
+    amp_sum = 0.0
+    for o in range(octaves):
+        amp = 2.0 ** -o
+        total = total + amp * value_noise3(x, y, z, period0 / 2.0 ** o, o, seed)
+        amp_sum += amp
+    return total / amp_sum

@@ -1,0 +1,325 @@
+"""Seeded synthetic scenes standing in for the paper's voxelised car model.
+
+Every scene is a pool of 8-byte nodes plus a slot table (child group and
+local root cell of every transformed subtree) and a function giving the
+forward, parent-relative 3x4 transform of every slot at a given frame.
+
+  config1  depth 6 (64^3) noisy sphere, one transformed level-1 node,
+           128x128 pinhole rays                          (small parity case)
+  config2  depth 10 (1024^3) fBm heightfield, 8 animated level-3 subtrees,
+           1920x1080 pinhole rays, 60 frames           (headline workload)
+  tiny     depth 3..5 random blobs with random nested transforms (pins)
+
+World units are leaf voxels of the root grid.  Rotations and scales pivot on
+the transformed cell's centre.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import camera as cam
+from . import octree as ot
+from . import xforms as xf
+from .hashing import Stream, hash_keys, to_unit
+from .noise import fbm2, fbm3
+
+NONE = 0xFFFFFFFF
+
+
+@dataclass
+class Scene:
+    name: str
+    nodes: np.ndarray                 # uint64 pool (transformed nodes flagged)
+    static_nodes: np.ndarray          # uint64 pool with every transform cleared
+    root: int
+    root_min: np.ndarray              # float32 [3]
+    root_size: float
+    max_depth: int
+    slot_child: np.ndarray            # uint32 [S]
+    slot_cell: np.ndarray             # float32 [S, 4] local root cell (min xyz, size)
+    slot_node: np.ndarray             # int64 [S] node carrying the slot
+    slot_parent: np.ndarray           # uint32 [S] enclosing slot or NONE (metadata for tests)
+    tree: ot.Tree                     # generation metadata of the pool
+    xform: Callable[[int], np.ndarray]  # frame -> float32 [S, 12]
+    camera: dict = field(default_factory=dict)
+    seed: int = 0
+
+    @property
+    def n_slots(self) -> int:
+        return int(self.slot_child.shape[0])
+
+    def rays(self, W=None, H=None, order="tiles"):
+        c = dict(self.camera)
+        W = W or c["W"]
+        H = H or c["H"]
+        return cam.pinhole_rays(c["eye"], c["target"], c["up"], c["fov"], W, H, order=order)
+
+    def frame_leaves(self):
+        """Solid leaves per frame for brute-force checks.
+
+        Returns {frame: (leaf index [n], box min [n,3], box size [n])} with
+        frame = NONE for the world and the slot id otherwise; boxes are in the
+        frame's local coordinates (equal to the static world cell here).
+        """
+        idx, mn, sz = ot.leaf_boxes(self.tree, self.root_min.astype(np.float64), float(self.root_size))
+        lev = self.tree.level[idx]
+        crd = self.tree.coord[idx]
+        owner = np.full(idx.shape[0], NONE, dtype=np.int64)
+        depth = np.full(idx.shape[0], -1, dtype=np.int64)
+        for s in range(self.n_slots):
+            nd = int(self.slot_node[s])
+            ls = int(self.tree.level[nd])
+            cs = self.tree.coord[nd]
+            inside = (lev > ls) & np.all((crd >> (lev - ls)[:, None]) == cs[None, :], axis=1)
+            better = inside & (ls > depth)
+            owner[better] = s
+            depth[better] = ls
+        out = {}
+        for f in np.unique(owner):
+            m = owner == f
+            out[int(f)] = (idx[m], mn[m], sz[m])
+        return out
+
+
+def _palette(level_y_frac, jitter):
+    bands = np.array([[70, 110, 60], [110, 150, 70], [150, 130, 90], [120, 120, 120], [235, 235, 240]], float)
+    b = np.clip((level_y_frac * len(bands)).astype(np.int64), 0, len(bands) - 1)
+    rgb = np.clip(bands[b] + (jitter[:, None] - 0.5) * 24.0, 0, 255).astype(np.uint64)
+    return rgb[:, 0] | (rgb[:, 1] << np.uint64(8)) | (rgb[:, 2] << np.uint64(16)) | (np.uint64(255) << np.uint64(24))
+
+
+def _colour_fn(K, seed):
+    def colour(l, c):
+        s = 1 << (K - l)
+        yfrac = (c[:, 1].astype(np.float64) + 0.5) * s / float(1 << K)
+        jit = to_unit(hash_keys(c[:, 0], c[:, 1], c[:, 2], l, seed, 7))
+        return _palette(yfrac, jit)
+    return colour
+
+
+def _slot_parents(tree, slot_node):
+    S = len(slot_node)
+    par = np.full(S, NONE, dtype=np.uint32)
+    for s in range(S):
+        ls = tree.level[slot_node[s]]
+        cs = tree.coord[slot_node[s]]
+        best = -1
+        for q in range(S):
+            lq = tree.level[slot_node[q]]
+            if lq < ls and np.all((cs >> (ls - lq)) == tree.coord[slot_node[q]]) and lq > best:
+                best = lq
+                par[s] = q
+    return par
+
+
+def _marked_scene(name, tree, K, root_size, cells, xform, camera, seed):
+    nodes, slot_child, slot_node = ot.mark_transformed(tree, cells)
+    S = len(cells)
+    slot_cell = np.zeros((S, 4), dtype=np.float32)
+    unit = root_size / float(1 << K)
+    for s, (l, xyz) in enumerate(cells):
+        size = unit * (1 << (K - l))
+        slot_cell[s, :3] = np.asarray(xyz, np.float64) * size
+        slot_cell[s, 3] = size
+    static = ot.clear_transformed(nodes, slot_child)
+    return Scene(name=name, nodes=nodes, static_nodes=static, root=0,
+                 root_min=np.zeros(3, np.float32), root_size=float(root_size), max_depth=K,
+                 slot_child=slot_child, slot_cell=slot_cell, slot_node=slot_node,
+                 slot_parent=_slot_parents(tree, slot_node), tree=tree, xform=xform,
+                 camera=camera, seed=seed)
+
+
+# ------------------------------------------------------------------ config 1
+
+def config1(seed: int = 1) -> Scene:
+    """Depth-6 noisy sphere; slot 0 on the level-1 node of octant 7 ([32,64)^3)
+    rotated +30 deg about y through its centre (48,48,48), then moved (5,0,2)."""
+    K = 6
+    n = 1 << K
+    g = np.arange(n, dtype=np.float64) + 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    r = np.sqrt((X - 32) ** 2 + (Y - 32) ** 2 + (Z - 32) ** 2)
+    occ = 24.0 - r + 4.0 * fbm3(X, Y, Z, 3, 16.0, seed) > 0
+    classify, _ = ot.dense_classifier(occ)
+    tree = ot.build_tree(K, classify, _colour_fn(K, seed))
+    A = xf.about_pivot(xf.rot_y(np.radians(30.0)), (48.0, 48.0, 48.0), (5.0, 0.0, 2.0))
+    A32 = xf.to_f32(A).reshape(1, 12)
+
+    def xform(frame: int = 0):
+        return A32.copy()
+
+    camera = dict(eye=(112.0, 96.0, 128.0), target=(32.0, 32.0, 32.0), up=(0.0, 1.0, 0.0), fov=45.0, W=128, H=128)
+    return _marked_scene("config1", tree, K, float(n), [(1, (1, 1, 1))], xform, camera, seed)
+
+
+# ------------------------------------------------------------------ config 2
+
+def heightfield(K: int, seed: int, base: float, amp: float, octaves: int, period0: float):
+    n = 1 << K
+    g = np.arange(n, dtype=np.float64) + 0.5
+    Xc, Zc = np.meshgrid(g, g, indexing="ij")
+    h = base + amp * fbm2(Xc, Zc, octaves, period0, seed)
+    return np.clip(np.ceil(h - 0.5), 0, n).astype(np.int64)
+
+
+def config2(seed: int = 2, frames: int = 60) -> Scene:
+    """Depth-10 fBm heightfield h = 512 + 256 fbm2 (6 octaves, P0 = 256); 8
+    level-3 subtrees animated: rotation about a seeded axis by 2 pi k f/60
+    (k in {1,2,3}) and per-axis scale 2^sin(2 pi f/60 + phase) about the cell
+    centre."""
+    K = 10
+    H = heightfield(K, seed, 512.0, 256.0, 6, 256.0)
+    tree = ot.build_tree(K, ot.heightfield_classifier(H, K), _colour_fn(K, seed))
+    st = Stream(seed, 11)
+    cand = np.nonzero((tree.level == 3) & (tree.kind == ot.PARTIAL))[0]
+    pick = []
+    while len(pick) < 8:
+        j = int(cand[st.integers(1, 0, cand.shape[0])[0]])
+        if j not in pick:
+            pick.append(j)
+    cells = [(3, tuple(int(v) for v in tree.coord[j])) for j in pick]
+    size = float(1 << (K - 3))
+    centres = [np.asarray(c[1], np.float64) * size + size / 2 for c in cells]
+    axes = []
+    for _ in range(8):
+        a = st.normal(3)
+        axes.append(a / np.linalg.norm(a))
+    ks = st.integers(8, 1, 4)
+    phases = st.uniform(24, 0.0, 2.0 * np.pi).reshape(8, 3)
+
+    def xform(frame: int = 0):
+        out = np.zeros((8, 12), np.float32)
+        for j in range(8):
+            R = xf.rot_axis_angle(axes[j], 2.0 * np.pi * ks[j] * frame / frames)
+            s = 2.0 ** np.sin(2.0 * np.pi * frame / frames + phases[j])
+            out[j] = xf.to_f32(xf.about_pivot(R @ np.diag(s), centres[j])).reshape(12)
+        return out
+
+    camera = dict(eye=(512.0, 1100.0, -400.0), target=(512.0, 500.0, 512.0), up=(0.0, 1.0, 0.0),
+                  fov=60.0, W=1920, H=1080)
+    return _marked_scene("config2", tree, K, float(1 << K), cells, xform, camera, seed)
+
+
+# ------------------------------------------------------------------ tiny scenes for pins
+
+def tiny_scene(seed: int, K: int = 4, n_slots: int = 2, nested: bool = True, density: float = 0.35,
+               scale_range=(0.5, 2.0), rotate: bool = True, translate: float = 0.0,
+               root_size: Optional[float] = None) -> Scene:
+    """Random blobby occupancy on a 2^K grid with random transformed nodes.
+
+    Slots sit on interior nodes at levels 1..K-2; with ``nested`` a later slot
+    may sit inside an earlier one's subtree.
+    """
+    n = 1 << K
+    st = Stream(seed, 21)
+    g = np.arange(n, dtype=np.float64) + 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    v = fbm3(X, Y, Z, 2, max(2.0, n / 2.0), seed)
+    occ = v > (1.0 - 2.0 * density) * 0.5
+    classify, _ = ot.dense_classifier(occ)
+    tree = ot.build_tree(K, classify, _colour_fn(K, seed))
+    if tree.n == 0:
+        raise ValueError("empty tiny scene")
+    rs = float(n) if root_size is None else float(root_size)
+    cells = []
+    used = []
+    inter = (tree.kind == ot.PARTIAL) & (tree.level >= 1) & (tree.level <= max(1, K - 2))
+    cand = np.nonzero(inter)[0]
+
+    def related(j, q):
+        lj, lq = int(tree.level[j]), int(tree.level[q])
+        if lj == lq:
+            return j == q
+        lo, hi = (q, j) if lq < lj else (j, q)
+        d = int(tree.level[hi]) - int(tree.level[lo])
+        return bool(np.all((tree.coord[hi] >> d) == tree.coord[lo]))
+
+    if nested and n_slots >= 2:
+        # a chain: slot 1 sits inside slot 0's subtree (and slot 2 inside slot 1 when possible)
+        top = np.nonzero(inter & (tree.level == 1))[0]
+        j0 = int(top[st.integers(1, 0, top.shape[0])[0]])
+        chain = [j0]
+        while len(chain) < min(n_slots, 3):
+            last = chain[-1]
+            sub = [int(q) for q in cand if tree.level[q] > tree.level[last] and related(int(q), last)]
+            if not sub:
+                break
+            chain.append(sub[int(st.integers(1, 0, len(sub))[0])])
+        used.extend(chain)
+    tries = 0
+    while len(used) < n_slots and tries < 400 and cand.size:
+        tries += 1
+        j = int(cand[st.integers(1, 0, cand.shape[0])[0]])
+        if any(related(j, q) for q in used):
+            continue
+        used.append(j)
+    cells = [(int(tree.level[j]), tuple(int(x) for x in tree.coord[j])) for j in used]
+    unit = rs / n
+    centres = [(np.asarray(c[1], np.float64) + 0.5) * unit * (1 << (K - c[0])) for c in cells]
+    mats = []
+    for s in range(len(cells)):
+        R = xf.random_rotation(st) if rotate else np.eye(3)
+        lo, hi = np.log2(scale_range[0]), np.log2(scale_range[1])
+        sc = 2.0 ** st.uniform(3, lo, hi)
+        tr = st.uniform(3, -translate, translate) * unit * (1 << (K - cells[s][0])) if translate else np.zeros(3)
+        mats.append(xf.to_f32(xf.about_pivot(R @ np.diag(sc), centres[s], tr)).reshape(12))
+    M = np.array(mats, np.float32).reshape(-1, 12)
+
+    def xform(frame: int = 0):
+        return M.copy()
+
+    sc = _marked_scene("tiny%d" % seed, tree, K, rs, cells, xform, {}, seed)
+    return sc
+
+
+def random_rays(seed: int, n: int, lo: float, hi: float, inside_frac: float = 0.2, tag: int = 31,
+                target_lo=None, target_hi=None):
+    """Rays aimed through the box [lo, hi]^3: origins on a sphere around it
+    (or inside it for ``inside_frac``), directions to random target points in
+    [target_lo, target_hi] (default: the box itself)."""
+    st = Stream(seed, tag)
+    c = 0.5 * (lo + hi)
+    R = (hi - lo) * 1.2
+    dirs = st.normal(3 * n).reshape(n, 3)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    org = c + R * dirs
+    inside = st.uniform(n) < inside_frac
+    org[inside] = lo + (hi - lo) * st.uniform(3 * int(inside.sum())).reshape(-1, 3)
+    tlo = np.full(3, lo, np.float64) if target_lo is None else np.asarray(target_lo, np.float64)
+    thi = np.full(3, hi, np.float64) if target_hi is None else np.asarray(target_hi, np.float64)
+    tgt = tlo + (thi - tlo) * st.uniform(3 * n).reshape(n, 3)
+    d = tgt - org
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, 0:3] = org
+    rays[:, 3] = 0.0
+    rays[:, 4:7] = d
+    rays[:, 7] = np.inf
+    return rays
+
+
+def from_occupancy(occ: np.ndarray, cells, fwd, root_size: Optional[float] = None, name: str = "occ",
+                   seed: int = 0) -> Scene:
+    """Scene from a dense boolean grid occ[x, y, z] with transformed nodes at
+    ``cells`` = [(level, (x, y, z))] and fixed forward maps ``fwd`` [S, 12]."""
+    classify, K = ot.dense_classifier(occ)
+    tree = ot.build_tree(K, classify, _colour_fn(K, seed))
+    rs = float(1 << K) if root_size is None else float(root_size)
+    F = np.asarray(fwd, np.float32).reshape(-1, 12) if len(cells) else np.zeros((0, 12), np.float32)
+
+    def xform(frame: int = 0):
+        return F.copy()
+
+    return _marked_scene(name, tree, K, rs, list(cells), xform, {}, seed)
+
+
+def blob_occupancy(K: int, seed: int, density: float = 0.4) -> np.ndarray:
+    """Random blobs on a 2^K grid (smooth noise thresholded)."""
+    n = 1 << K
+    g = np.arange(n, dtype=np.float64) + 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    v = fbm3(X, Y, Z, 2, max(2.0, n / 2.0), seed)
+    return v > (1.0 - 2.0 * density) * 0.5
