@@ -1,0 +1,186 @@
+/*
+ * svo.h -- C ABI of the animated sparse-voxel-octree ray tracer for MI355X
+ * (gfx950).
+ *
+ * The library traces rays R(t) = o + t d, t in [tmin, tmax] (paper Eq. 1)
+ * through one octree pool whose interior nodes may carry affine transforms.
+ * A transformed node starts a new frame: its subtree is a rigid body placed
+ * by a parent-relative forward map A_s (rotation, translation, anisotropic
+ * scale, or any invertible affine map).  The octree is never rebuilt when
+ * transforms change; each ray is mapped into a frame's local coordinates
+ * instead (Sec. 3: inverse-transform the ray, Fig. 1; Eq. 2-3: the local ray
+ * keeps the world parameter t).  The first hit reports the voxel id, t and
+ * the surface normal, the per-pixel fields of the paper's hit buffer
+ * (Sec. 4.3).
+ *
+ * Conventions for every entry point:
+ *   - Return SVO_OK (0) or a negative svo_status; nothing throws or aborts
+ *     across the ABI.  svo_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - "host" pointers are read during the call only and may be reused on
+ *     return; "device" pointers must stay valid until the stream work that
+ *     uses them has completed.  The caller owns both.  The library owns the
+ *     device copies of pools and transform tables.
+ *   - Work is stream ordered on the hipStream_t passed as `void* stream`
+ *     (NULL = the null stream).  Calls on one context are not thread safe.
+ *
+ * ------------------------------------------------------------------------
+ * Pool format (one uint64 per node, little endian):
+ *   bits  0..7   child mask m; octant i = x | y << 1 | z << 2, where x, y, z
+ *                select the upper half of the cell along that axis
+ *   bits  8..31  c24: offset of the first child relative to this node
+ *   bits 32..63  word1
+ *   m == 0                  solid leaf; the whole cell is solid; word1 is
+ *                           free (RGBA8 colour by convention); c24 unused
+ *   m != 0, word1 bit 31    transformed node; slot s = word1 & 0x7fffffff;
+ *                           children start at slot_child[s]; c24 unused
+ *   m != 0, c24 == 0xffffff far pointer: children start at word1
+ *   m != 0, otherwise       children start at node_index + c24 (c24 >= 1)
+ * The k-th set bit of m (in octant order) is the child at start + k.  The
+ * cell of a child is the parent cell halved on every axis; the world root
+ * cell is [root_min, root_min + root_size)^3 and the root frame of slot s is
+ * the cube slot_cell[s] = (min x, min y, min z, size) in that slot's local
+ * coordinates.  A node reached through more than one parent (DAG sharing,
+ * instancing) must not contain transformed nodes.  Leaves are boxes closed
+ * on every side.
+ *
+ * Hit semantics (identical to the CPU oracle's definition):
+ *   frame F0 = the world tree without its transformed subtrees; frame F_s =
+ *   the subtree of slot s without nested transformed subtrees; the world map
+ *   of F_s is W_s = W_parent(s) o A_s.  A leaf box B of frame F is hit at
+ *   t = max(t_near, tmin) when the ray meets W_F(B) within [tmin, tmax];
+ *   the result is the smallest such t over all frames (ties: smaller slot,
+ *   then smaller node index).  id = node index of the leaf, inst = slot of
+ *   its frame (SVO_NONE for F0), normal = outward normal of the entry face
+ *   (the inverse transpose of W_F applied to the local face normal,
+ *   normalised), zero when the ray starts inside the leaf.  A miss returns
+ *   id = inst = SVO_NONE, t = +inf, normal = 0.  Rays with a non-finite
+ *   component, a zero direction or tmin > tmax miss.  The direction is never
+ *   renormalised: t is in units of the caller's d.
+ *
+ * The device computes in FP32.  Rays within a few ulps of an edge, a face
+ * or a tie may resolve to a neighbouring voxel (a "grazing" ray).
+ */
+#ifndef SVO_H
+#define SVO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SVO_ABI_VERSION 1
+
+typedef enum {
+    SVO_OK = 0,
+    SVO_EINVAL = -1,   /* invalid argument, malformed pool or singular transform */
+    SVO_ENOMEM = -2,   /* host or device allocation failed */
+    SVO_EDEVICE = -3,  /* a HIP runtime call failed */
+    SVO_ERANGE = -4,   /* a size is beyond a documented limit */
+    SVO_EBUSY = -5,    /* resource still in use */
+    SVO_ESTATE = -6    /* call not valid in the current state */
+} svo_status;
+
+#define SVO_NONE 0xFFFFFFFFu        /* miss id / inst; world frame; empty world root */
+#define SVO_STEP_LIMIT 0xFFFFFFFEu  /* id of a ray that exceeded the per-ray step limit */
+#define SVO_MAX_DEPTH 20u           /* levels below any frame root */
+#define SVO_MAX_SLOTS 4096u         /* transform slots per scene */
+#define SVO_MAX_OVERFLOW 64u        /* slots per scene whose moved content leaves its static cell */
+
+typedef struct svo_ctx svo_ctx;     /* opaque: device, pools, transform tables, work queues */
+typedef uint32_t svo_scene;         /* scene handle, 0 is never valid */
+
+/* What validation found out about a pool (host-only; svo_validate). */
+typedef struct {
+    uint64_t n_nodes;
+    uint32_t n_frames;        /* 1 (world) + number of referenced slots */
+    uint32_t world_height;    /* levels below the world root (0: root is a leaf or the world is empty) */
+    uint32_t max_height;      /* largest frame height */
+    uint32_t max_nesting;     /* deepest chain of nested slots (0: no slot) */
+    uint32_t n_shared;        /* nodes referenced from more than one parent */
+    uint32_t reserved;
+} svo_pool_info;
+
+/* Kernel configuration; svo_tune() picks one, svo_set_config() sets one.
+   Zero fields select the library defaults. */
+typedef struct {
+    uint32_t waves_per_block;   /* 1..16 wavefronts (64 lanes) per work-group */
+    uint32_t blocks_per_cu;     /* resident work-groups per compute unit for the persistent grid */
+    uint32_t lds_cache_nodes;   /* first N pool nodes (the top levels, breadth-first) kept in LDS */
+    uint32_t refill_lanes;      /* 0: a wave takes 64-ray tiles; k>0: refill once >= k lanes are idle */
+    uint32_t step_limit;        /* node steps per ray before SVO_STEP_LIMIT */
+    uint32_t reserved[3];
+} svo_config;
+
+/* ABI version the library was built with (SVO_ABI_VERSION). */
+int svo_abi_version(void);
+
+/* Message for the calling thread's last failed call ("" if none).  The
+   string stays valid until the thread's next library call. */
+const char* svo_last_error(void);
+
+/* Create a context on HIP device `device_ordinal` (makes it current while
+   the library works).  *out is set to NULL on failure. */
+int svo_create(svo_ctx** out, int device_ordinal);
+
+/* Free every scene, buffer and stream resource of the context after
+   waiting for its device work.  NULL is a no-op. */
+void svo_destroy(svo_ctx* ctx);
+
+/* Host-only pool check (no device needed).  nodes: host, n_nodes entries.
+   root: index of the world root, or SVO_NONE for an empty world.
+   max_depth: reject frames deeper than this (<= SVO_MAX_DEPTH).
+   slot_child: host, n_slots child-group starts.  Checks every rule of the
+   pool format above: child groups inside the pool, c24 != 0, slots in range
+   and used by at most one node, no cycles, no transformed root, depth, and
+   the DAG rule.  info may be NULL.  SVO_EINVAL on a malformed pool,
+   SVO_ERANGE on a limit. */
+int svo_validate(const uint64_t* nodes, uint64_t n_nodes, uint32_t root, uint32_t max_depth,
+                 const uint32_t* slot_child, uint32_t n_slots, svo_pool_info* info);
+
+/* Validate a pool and copy it to the device (synchronous).  root_min[3],
+   root_size: world root cell.  slot_cell: host, n_slots * 4 floats (local
+   root cell min xyz, edge length > 0).  Every slot starts with the identity
+   transform.  *out receives the scene handle. */
+int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t root, const float root_min[3],
+               float root_size, uint32_t max_depth, const uint32_t* slot_child, const float* slot_cell,
+               uint32_t n_slots, svo_scene* out);
+
+/* Release a scene's device memory after its queued work has finished. */
+int svo_free_scene(svo_ctx* ctx, svo_scene scene);
+
+/* Device bytes the scene holds (pool + transform tables), for admission. */
+int svo_scene_bytes(svo_ctx* ctx, svo_scene scene, uint64_t* bytes);
+
+/* Set the parent-relative forward maps of slots [first_slot, first_slot +
+   count).  fwd_3x4: host, count * 12 floats, row-major 3x4 [L | b] with
+   x_parent = L x_local + b (paper Eq. 3 inverts this per frame; nested slots
+   compose).  The library composes and inverts in FP64 on the host, packs one
+   64-byte FP32 record per frame and copies the whole table on `stream`;
+   traces enqueued on `stream` afterwards see the new transforms, earlier
+   ones the old (two device tables alternate).  SVO_EINVAL on a non-finite
+   or singular map, on slots out of range, or when more than
+   SVO_MAX_OVERFLOW slots leave their static cell. */
+int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint32_t count, const float* fwd_3x4,
+                       void* stream);
+
+/* Trace n rays.  rays: device, n * 8 floats per ray (ox, oy, oz, tmin, dx,
+   dy, dz, tmax), 16-byte aligned.  Outputs (device, n entries each): out_id
+   (required), out_inst (nullable), out_t (required), out_normal (nullable,
+   n * 3 floats).  n == 0 is a no-op.  The kernel never reads outside the
+   pool, the rays or the outputs; ray contents are not validated (see the
+   hit semantics above).  Traces on different streams of one context may
+   overlap (each stream has its own work queue, up to 64 streams). */
+int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                   uint32_t* out_inst, float* out_t, float* out_normal, void* stream);
+
+/* Current kernel configuration of the context / replace it (validated). */
+int svo_get_config(svo_ctx* ctx, svo_config* cfg);
+int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVO_H */

@@ -1,0 +1,708 @@
+// Host side of the C ABI: contexts, pool validation and upload, per-frame
+// transform preparation (FP64 compose + invert, FP32 frame records) and
+// kernel launches.  Every entry point returns a status code; nothing throws
+// across the ABI.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "svo.h"
+#include "svo_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(SVO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr uint32_t kFar = 0xFFFFFFu;
+constexpr uint32_t kXform = 0x80000000u;
+constexpr uint32_t kMaxStreams = 64;
+
+inline uint32_t nd_mask(uint64_t w) { return (uint32_t)(w & 0xFFu); }
+inline uint32_t nd_c24(uint64_t w) { return (uint32_t)((w >> 8) & 0xFFFFFFu); }
+inline uint32_t nd_w1(uint64_t w) { return (uint32_t)(w >> 32); }
+inline bool nd_leaf(uint64_t w) { return nd_mask(w) == 0; }
+inline bool nd_xform(uint64_t w) { return nd_mask(w) != 0 && (nd_w1(w) & kXform); }
+inline int popc(uint32_t v) { return __builtin_popcount(v); }
+
+// ------------------------------------------------------------------ pool analysis
+
+struct Analysis {
+    uint32_t n_frames = 1, world_height = 0, max_height = 0, max_nesting = 0, n_shared = 0;
+    std::vector<int32_t> slot_parent;   // -1 world, -2 unused, else slot
+    std::vector<uint32_t> slot_node;
+    std::vector<uint32_t> slot_height;  // levels below the slot's frame root
+    std::vector<uint32_t> slot_level;   // level of the transformed node in its parent frame
+    std::vector<std::array<uint32_t, 3>> slot_coord;
+    std::vector<uint32_t> slot_mask;
+    std::vector<uint32_t> order;        // used slots, parents before children
+};
+
+// Children of node i: start index and count; false if i is a leaf.
+inline bool children_of(const uint64_t* nodes, uint64_t i, const uint32_t* slot_child, uint64_t& start, int& count) {
+    const uint64_t w = nodes[i];
+    if (nd_leaf(w)) return false;
+    count = popc(nd_mask(w));
+    if (nd_xform(w)) {
+        start = slot_child[nd_w1(w) & 0x7FFFFFFFu];
+    } else if (nd_c24(w) == kFar) {
+        start = nd_w1(w);
+    } else {
+        start = i + nd_c24(w);
+    }
+    return true;
+}
+
+int analyse(const uint64_t* nodes, uint64_t n, uint32_t root, uint32_t max_depth, const uint32_t* slot_child,
+            uint32_t n_slots, Analysis& A) {
+    if (max_depth > SVO_MAX_DEPTH) return fail(SVO_ERANGE, "max_depth %u exceeds %u", max_depth, SVO_MAX_DEPTH);
+    if (n_slots > SVO_MAX_SLOTS) return fail(SVO_ERANGE, "n_slots %u exceeds %u", n_slots, SVO_MAX_SLOTS);
+    if (n >= 0xFFFFFFFEull) return fail(SVO_ERANGE, "n_nodes must be below 2^32 - 2");
+    if (n && !nodes) return fail(SVO_EINVAL, "nodes is NULL");
+    if (n_slots && !slot_child) return fail(SVO_EINVAL, "slot_child is NULL");
+    A = Analysis();
+    A.slot_parent.assign(n_slots, -2);
+    A.slot_node.assign(n_slots, 0);
+    A.slot_height.assign(n_slots, 0);
+    A.slot_level.assign(n_slots, 0);
+    A.slot_coord.assign(n_slots, {0, 0, 0});
+    A.slot_mask.assign(n_slots, 0);
+    if (root == SVO_NONE) return SVO_OK;
+    if (root >= n) return fail(SVO_EINVAL, "root %u out of range (%llu nodes)", root, (unsigned long long)n);
+    if (nd_xform(nodes[root])) return fail(SVO_EINVAL, "the world root may not be a transformed node");
+
+    // check every node's child reference before any traversal uses it
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t w = nodes[i];
+        if (nd_leaf(w)) continue;
+        const uint64_t cnt = (uint64_t)popc(nd_mask(w));
+        uint64_t start;
+        if (nd_xform(w)) {
+            const uint32_t s = nd_w1(w) & 0x7FFFFFFFu;
+            if (s >= n_slots) return fail(SVO_EINVAL, "node %llu: slot %u out of range", (unsigned long long)i, s);
+            start = slot_child[s];
+        } else if (nd_c24(w) == kFar) {
+            start = nd_w1(w);
+        } else {
+            if (nd_c24(w) == 0) return fail(SVO_EINVAL, "node %llu: child offset 0", (unsigned long long)i);
+            if (nd_w1(w) != 0) return fail(SVO_EINVAL, "node %llu: word1 must be 0 with a relative offset", (unsigned long long)i);
+            start = i + nd_c24(w);
+        }
+        if (start + cnt > n) return fail(SVO_EINVAL, "node %llu: child group out of range", (unsigned long long)i);
+    }
+
+    // post-order DFS: cycles, heights, "contains a transformed node", in-degree
+    std::vector<uint8_t> color(n, 0), height(n, 0), has_xf(n, 0), refs(n, 0);
+    std::vector<uint8_t> slot_h(n_slots, 0);
+    std::vector<std::pair<uint32_t, uint32_t>> st;
+    st.reserve(64);
+    st.push_back({root, 0});
+    color[root] = 1;
+    while (!st.empty()) {
+        auto& top = st.back();
+        const uint32_t i = top.first;
+        uint64_t start;
+        int cnt = 0;
+        const bool inner = children_of(nodes, i, slot_child, start, cnt);
+        if (inner && (int)top.second < cnt) {
+            const uint32_t c = (uint32_t)(start + top.second);
+            ++top.second;
+            if (refs[c] < 2) ++refs[c];
+            if (color[c] == 1) return fail(SVO_EINVAL, "cycle through node %u", c);
+            if (color[c] == 0) {
+                color[c] = 1;
+                st.push_back({c, 0});
+            }
+            continue;
+        }
+        // all children done
+        uint32_t h = 0, x = 0;
+        if (inner) {
+            for (int k = 0; k < cnt; ++k) {
+                const uint32_t c = (uint32_t)(start + k);
+                h = std::max<uint32_t>(h, 1u + height[c]);
+                x |= has_xf[c] | (nd_xform(nodes[c]) ? 1u : 0u);
+            }
+        }
+        if (h > max_depth) return fail(SVO_ERANGE, "a frame is deeper than max_depth %u", max_depth);
+        if (nd_xform(nodes[i])) {
+            const uint32_t s = nd_w1(nodes[i]) & 0x7FFFFFFFu;
+            slot_h[s] = (uint8_t)h;
+            height[i] = 0;  // an empty cell for the frame around it
+            has_xf[i] = 1;
+        } else {
+            height[i] = (uint8_t)h;
+            has_xf[i] = (uint8_t)x;
+        }
+        color[i] = 2;
+        st.pop_back();
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        if (refs[i] >= 2) {
+            ++A.n_shared;
+            if (has_xf[i]) return fail(SVO_EINVAL, "node %llu is shared but contains a transformed node", (unsigned long long)i);
+        }
+    }
+    A.world_height = height[root];
+    A.max_height = A.world_height;
+
+    // top-down walk along paths that lead to transformed nodes: parent
+    // frame, level and cell of every transformed node (paths are unique)
+    struct Item { uint32_t node; int32_t frame; uint32_t level, x, y, z, nest; };
+    std::vector<Item> q;
+    q.push_back({root, -1, 0, 0, 0, 0, 0});
+    while (!q.empty()) {
+        const Item it = q.back();
+        q.pop_back();
+        uint64_t start;
+        int cnt;
+        if (!children_of(nodes, it.node, slot_child, start, cnt)) continue;
+        const uint32_t mask = nd_mask(nodes[it.node]);
+        int k = 0;
+        for (uint32_t o = 0; o < 8; ++o) {
+            if (!(mask & (1u << o))) continue;
+            const uint32_t c = (uint32_t)(start + k++);
+            if (!has_xf[c]) continue;
+            const uint32_t cx = 2 * it.x + (o & 1u), cy = 2 * it.y + ((o >> 1) & 1u), cz = 2 * it.z + ((o >> 2) & 1u);
+            if (nd_xform(nodes[c])) {
+                const uint32_t s = nd_w1(nodes[c]) & 0x7FFFFFFFu;
+                if (A.slot_parent[s] != -2) return fail(SVO_EINVAL, "slot %u is used by two nodes", s);
+                A.slot_parent[s] = it.frame;
+                A.slot_node[s] = c;
+                A.slot_level[s] = it.level + 1;
+                A.slot_coord[s] = {cx, cy, cz};
+                A.slot_mask[s] = nd_mask(nodes[c]);
+                A.slot_height[s] = slot_h[s];
+                A.max_height = std::max(A.max_height, (uint32_t)slot_h[s]);
+                A.max_nesting = std::max(A.max_nesting, it.nest + 1);
+                A.order.push_back(s);
+                A.n_frames++;
+                q.push_back({c, (int32_t)s, 0, 0, 0, 0, it.nest + 1});
+            } else {
+                q.push_back({c, it.frame, it.level + 1, cx, cy, cz, it.nest});
+            }
+        }
+    }
+    // parents before children
+    std::vector<uint32_t> depth(n_slots, 0);
+    for (uint32_t s : A.order) {
+        uint32_t d = 0;
+        for (int32_t p = A.slot_parent[s]; p >= 0; p = A.slot_parent[p]) ++d;
+        depth[s] = d;
+    }
+    std::stable_sort(A.order.begin(), A.order.end(), [&](uint32_t a, uint32_t b) { return depth[a] < depth[b]; });
+    return SVO_OK;
+}
+
+// ------------------------------------------------------------------ FP64 affine maps
+
+struct Aff {
+    double m[3][4];
+};
+
+Aff aff_identity() {
+    Aff a;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c) a.m[r][c] = (r == c) ? 1.0 : 0.0;
+    return a;
+}
+
+// x -> P(C(x))
+Aff aff_mul(const Aff& P, const Aff& C) {
+    Aff o;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 4; ++c) {
+            double v = P.m[r][0] * C.m[0][c] + P.m[r][1] * C.m[1][c] + P.m[r][2] * C.m[2][c];
+            if (c == 3) v += P.m[r][3];
+            o.m[r][c] = v;
+        }
+    }
+    return o;
+}
+
+// Inverse by elimination with partial pivoting; false if (near) singular.
+bool aff_inverse(const Aff& A, Aff& I) {
+    double a[3][6];
+    double scale = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) scale = std::max(scale, std::fabs(A.m[r][c]));
+    if (!(scale > 0.0) || !std::isfinite(scale)) return false;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 6; ++c) a[r][c] = (c < 3) ? A.m[r][c] : ((c - 3 == r) ? 1.0 : 0.0);
+    for (int col = 0; col < 3; ++col) {
+        int p = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (std::fabs(a[r][col]) > std::fabs(a[p][col])) p = r;
+        if (std::fabs(a[p][col]) <= 1e-12 * scale) return false;
+        if (p != col)
+            for (int c = 0; c < 6; ++c) std::swap(a[p][c], a[col][c]);
+        const double inv = 1.0 / a[col][col];
+        for (int c = 0; c < 6; ++c) a[col][c] *= inv;
+        for (int r = 0; r < 3; ++r) {
+            if (r == col || a[r][col] == 0.0) continue;
+            const double f = a[r][col];
+            for (int c = 0; c < 6; ++c) a[r][c] -= f * a[col][c];
+        }
+    }
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) I.m[r][c] = a[r][3 + c];
+        I.m[r][3] = -(I.m[r][0] * A.m[0][3] + I.m[r][1] * A.m[1][3] + I.m[r][2] * A.m[2][3]);
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ context / scenes
+
+struct Scene {
+    uint64_t n_nodes = 0;
+    uint32_t root = SVO_NONE;
+    float root_min[3] = {0, 0, 0};
+    float root_size = 1;
+    uint32_t n_slots = 0;
+    Analysis an;
+    std::vector<uint32_t> slot_child;
+    std::vector<float> slot_cell;
+    std::vector<Aff> fwd;               // parent-relative forward maps
+    uint32_t world_child = 0;
+    uint32_t world_mask = 0;
+    uint64_t* d_nodes = nullptr;
+    svo::FrameRec* d_frames[2] = {nullptr, nullptr};
+    svo::FrameRec* h_stage[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int cur = 0;                        // table the next trace reads
+    uint32_t n_frames = 1;              // records in the current table
+    uint32_t n_cand = 0;
+    uint32_t stack_levels = 1;
+    uint64_t bytes = 0;
+};
+
+}  // namespace
+
+struct svo_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t max_lds = 0;
+    svo_config cfg{};
+    uint32_t next_scene = 1;
+    std::map<uint32_t, std::unique_ptr<Scene>> scenes;
+    uint32_t* d_queue = nullptr;                // kMaxStreams pairs of counters
+    std::map<hipStream_t, uint32_t> stream_slot;
+};
+
+namespace {
+
+svo_config default_config() {
+    svo_config c{};
+    c.waves_per_block = 4;
+    c.blocks_per_cu = 4;
+    c.lds_cache_nodes = 1024;
+    c.refill_lanes = 0;
+    c.step_limit = 1u << 20;
+    return c;
+}
+
+int check_config(const svo_config& c) {
+    if (c.waves_per_block < 1 || c.waves_per_block > 8) return fail(SVO_EINVAL, "waves_per_block must be 1..8");
+    if (c.blocks_per_cu < 1 || c.blocks_per_cu > 32) return fail(SVO_EINVAL, "blocks_per_cu must be 1..32");
+    if (c.lds_cache_nodes > 16384) return fail(SVO_EINVAL, "lds_cache_nodes must be <= 16384");
+    if (c.step_limit < 1) return fail(SVO_EINVAL, "step_limit must be >= 1");
+    return SVO_OK;
+}
+
+void free_scene(Scene& s) {
+    if (s.d_nodes) (void)hipFree(s.d_nodes);
+    for (int k = 0; k < 2; ++k) {
+        if (s.d_frames[k]) (void)hipFree(s.d_frames[k]);
+        if (s.h_stage[k]) (void)hipHostFree(s.h_stage[k]);
+        if (s.ev[k]) (void)hipEventDestroy(s.ev[k]);
+    }
+    s.d_nodes = nullptr;
+}
+
+Scene* find_scene(svo_ctx* ctx, svo_scene h) {
+    auto it = ctx->scenes.find(h);
+    return it == ctx->scenes.end() ? nullptr : it->second.get();
+}
+
+// Compose, invert and pack the frame table into `out` (host).  Frames:
+// [0] world, then every referenced slot (all are candidates for now).
+int build_frames(Scene& S, svo::FrameRec* out, uint32_t& n_frames, uint32_t& n_cand) {
+    const Analysis& A = S.an;
+    // world
+    svo::FrameRec& W = out[0];
+    std::memset(&W, 0, sizeof W);
+    const uint32_t K0 = A.world_height;
+    const double g0 = std::ldexp(1.0, (int)K0) / (double)S.root_size;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) W.m[4 * r + c] = (r == c) ? (float)g0 : 0.0f;
+        W.m[4 * r + 3] = (float)(-(double)S.root_min[r] * g0);
+    }
+    W.inst = SVO_NONE;
+    W.root = S.root;
+    if (S.root == SVO_NONE) {
+        W.info = svo::FR_EMPTY;
+    } else {
+        W.info = (K0 << svo::FR_K_SHIFT);
+        if (K0 == 0) W.info |= svo::FR_ROOT_LEAF;
+        W.child = S.world_child;
+        W.info |= S.world_mask;
+    }
+    n_frames = 1;
+    std::vector<Aff> world(S.n_slots);
+    for (uint32_t s : A.order) {
+        const int32_t p = A.slot_parent[s];
+        world[s] = aff_mul(p < 0 ? aff_identity() : world[p], S.fwd[s]);
+    }
+    for (uint32_t s : A.order) {
+        Aff inv;
+        if (!aff_inverse(world[s], inv)) return fail(SVO_EINVAL, "transform of slot %u is singular", s);
+        const float* cell = &S.slot_cell[4 * s];
+        const uint32_t K = A.slot_height[s];
+        const double g = std::ldexp(1.0, (int)K) / (double)cell[3];
+        svo::FrameRec& F = out[n_frames++];
+        std::memset(&F, 0, sizeof F);
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) F.m[4 * r + c] = (float)(g * inv.m[r][c]);
+            F.m[4 * r + 3] = (float)(g * (inv.m[r][3] - (double)cell[r]));
+        }
+        F.child = S.slot_child[s];
+        F.info = A.slot_mask[s] | (K << svo::FR_K_SHIFT);
+        F.inst = s;
+        F.root = A.slot_node[s];
+        // containment of the moved cell in its static cell (parent frame)
+        const int32_t p = A.slot_parent[s];
+        double pmin[3], psize;
+        if (p < 0) {
+            for (int a = 0; a < 3; ++a) pmin[a] = S.root_min[a];
+            psize = S.root_size;
+        } else {
+            for (int a = 0; a < 3; ++a) pmin[a] = S.slot_cell[4 * p + a];
+            psize = S.slot_cell[4 * p + 3];
+        }
+        const double csize = psize / std::ldexp(1.0, (int)A.slot_level[s]);
+        bool inside = true;
+        for (int k = 0; k < 8 && inside; ++k) {
+            double x[3];
+            for (int a = 0; a < 3; ++a) x[a] = cell[a] + (((k >> a) & 1) ? cell[3] : 0.0);
+            for (int r = 0; r < 3; ++r) {
+                const double v = S.fwd[s].m[r][0] * x[0] + S.fwd[s].m[r][1] * x[1] + S.fwd[s].m[r][2] * x[2] +
+                                 S.fwd[s].m[r][3];
+                const double lo = pmin[r] + A.slot_coord[s][r] * csize;
+                const double margin = 1e-5 * csize;
+                if (v < lo + margin || v > lo + csize - margin) inside = false;
+            }
+        }
+        if (inside) F.info |= svo::FR_CONTAINED;
+    }
+    n_cand = n_frames - 1;
+    if (n_cand > SVO_MAX_OVERFLOW)
+        return fail(SVO_ERANGE, "%u transformed subtrees exceed the %u candidate frames a ray can merge", n_cand,
+                    SVO_MAX_OVERFLOW);
+    return SVO_OK;
+}
+
+int upload_frames(Scene& S, hipStream_t stream) {
+    const int k = S.cur ^ 1;
+    // the staging buffer may still feed an earlier copy
+    HIP_TRY(hipEventSynchronize(S.ev[k]));
+    uint32_t nf = 0, nc = 0;
+    int rc = build_frames(S, S.h_stage[k], nf, nc);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(S.d_frames[k], S.h_stage[k], (size_t)nf * sizeof(svo::FrameRec), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipEventRecord(S.ev[k], stream));
+    S.cur = k;
+    S.n_frames = nf;
+    S.n_cand = nc;
+    return SVO_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int svo_abi_version(void) { return SVO_ABI_VERSION; }
+
+const char* svo_last_error(void) { return g_err.c_str(); }
+
+int svo_validate(const uint64_t* nodes, uint64_t n_nodes, uint32_t root, uint32_t max_depth,
+                 const uint32_t* slot_child, uint32_t n_slots, svo_pool_info* info) {
+    try {
+        Analysis A;
+        const int rc = analyse(nodes, n_nodes, root, max_depth, slot_child, n_slots, A);
+        if (rc) return rc;
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            info->n_nodes = n_nodes;
+            info->n_frames = A.n_frames;
+            info->world_height = A.world_height;
+            info->max_height = A.max_height;
+            info->max_nesting = A.max_nesting;
+            info->n_shared = A.n_shared;
+        }
+        return SVO_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SVO_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(SVO_EINVAL, "unexpected error");
+    }
+}
+
+int svo_create(svo_ctx** out, int device_ordinal) {
+    if (!out) return fail(SVO_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device_ordinal < 0 || device_ordinal >= n) return fail(SVO_EINVAL, "device %d out of range (%d)", device_ordinal, n);
+    HIP_TRY(hipSetDevice(device_ordinal));
+    std::unique_ptr<svo_ctx> c(new (std::nothrow) svo_ctx());
+    if (!c) return fail(SVO_ENOMEM, "out of host memory");
+    c->device = device_ordinal;
+    HIP_TRY(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal));
+    int lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device_ordinal));
+    c->max_lds = (size_t)lds;
+    c->cfg = default_config();
+    HIP_TRY(hipMalloc((void**)&c->d_queue, kMaxStreams * 2 * sizeof(uint32_t)));
+    HIP_TRY(hipMemset(c->d_queue, 0, kMaxStreams * 2 * sizeof(uint32_t)));
+    HIP_TRY(hipDeviceSynchronize());
+    *out = c.release();
+    return SVO_OK;
+}
+
+void svo_destroy(svo_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->scenes) free_scene(*kv.second);
+    ctx->scenes.clear();
+    if (ctx->d_queue) (void)hipFree(ctx->d_queue);
+    delete ctx;
+}
+
+int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t root, const float root_min[3],
+               float root_size, uint32_t max_depth, const uint32_t* slot_child, const float* slot_cell,
+               uint32_t n_slots, svo_scene* out) {
+    if (!ctx || !out) return fail(SVO_EINVAL, "ctx and out must not be NULL");
+    if (!root_min) return fail(SVO_EINVAL, "root_min is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(root_min[a])) return fail(SVO_EINVAL, "root_min must be finite");
+    if (!(root_size > 0.0f) || !std::isfinite(root_size)) return fail(SVO_EINVAL, "root_size must be finite and > 0");
+    if (n_slots && !slot_cell) return fail(SVO_EINVAL, "slot_cell is NULL");
+    for (uint32_t s = 0; s < n_slots; ++s) {
+        for (int a = 0; a < 4; ++a)
+            if (!std::isfinite(slot_cell[4 * s + a])) return fail(SVO_EINVAL, "slot_cell[%u] must be finite", s);
+        if (!(slot_cell[4 * s + 3] > 0.0f)) return fail(SVO_EINVAL, "slot_cell[%u] size must be > 0", s);
+    }
+    try {
+        std::unique_ptr<Scene> S(new Scene());
+        int rc = analyse(nodes, n_nodes, root, max_depth, slot_child, n_slots, S->an);
+        if (rc) return rc;
+        S->n_nodes = n_nodes;
+        S->root = root;
+        for (int a = 0; a < 3; ++a) S->root_min[a] = root_min[a];
+        S->root_size = root_size;
+        S->n_slots = n_slots;
+        S->slot_child.assign(slot_child, slot_child + n_slots);
+        S->slot_cell.assign(slot_cell, slot_cell + 4 * (size_t)n_slots);
+        S->fwd.assign(n_slots, aff_identity());
+        if (root != SVO_NONE && !nd_leaf(nodes[root])) {
+            uint64_t st;
+            int cnt;
+            children_of(nodes, root, S->slot_child.data(), st, cnt);
+            S->world_child = (uint32_t)st;
+            S->world_mask = nd_mask(nodes[root]);
+        }
+        S->stack_levels = std::max<uint32_t>(S->an.max_height, 1) + 1;
+        HIP_TRY(hipSetDevice(ctx->device));
+        const size_t nb = std::max<uint64_t>(n_nodes, 1) * sizeof(uint64_t);
+        if (hipMalloc((void**)&S->d_nodes, nb) != hipSuccess) {
+            free_scene(*S);
+            return fail(SVO_ENOMEM, "device allocation of %zu bytes failed", nb);
+        }
+        const uint32_t max_frames = S->an.n_frames;
+        const size_t fb = (size_t)max_frames * sizeof(svo::FrameRec);
+        for (int k = 0; k < 2; ++k) {
+            if (hipMalloc((void**)&S->d_frames[k], fb) != hipSuccess ||
+                hipHostMalloc((void**)&S->h_stage[k], fb, hipHostMallocDefault) != hipSuccess ||
+                hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming) != hipSuccess) {
+                free_scene(*S);
+                return fail(SVO_ENOMEM, "allocation of frame tables failed");
+            }
+        }
+        if (n_nodes) {
+            hipError_t e = hipMemcpy(S->d_nodes, nodes, n_nodes * sizeof(uint64_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                free_scene(*S);
+                return fail(SVO_EDEVICE, "pool copy failed: %s", hipGetErrorString(e));
+            }
+        }
+        for (int k = 0; k < 2; ++k) (void)hipEventRecord(S->ev[k], 0);
+        rc = upload_frames(*S, 0);
+        if (rc == SVO_OK && hipStreamSynchronize(0) != hipSuccess) rc = fail(SVO_EDEVICE, "frame upload failed");
+        if (rc) {
+            free_scene(*S);
+            return rc;
+        }
+        S->bytes = nb + 2 * fb;
+        const uint32_t h = ctx->next_scene++;
+        ctx->scenes[h] = std::move(S);
+        *out = h;
+        return SVO_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SVO_ENOMEM, "out of host memory");
+    }
+}
+
+int svo_free_scene(svo_ctx* ctx, svo_scene scene) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    auto it = ctx->scenes.find(scene);
+    if (it == ctx->scenes.end()) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    free_scene(*it->second);
+    ctx->scenes.erase(it);
+    return SVO_OK;
+}
+
+int svo_scene_bytes(svo_ctx* ctx, svo_scene scene, uint64_t* bytes) {
+    if (!ctx || !bytes) return fail(SVO_EINVAL, "ctx and bytes must not be NULL");
+    Scene* S = find_scene(ctx, scene);
+    if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    *bytes = S->bytes;
+    return SVO_OK;
+}
+
+int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint32_t count, const float* fwd_3x4,
+                       void* stream) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    Scene* S = find_scene(ctx, scene);
+    if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    if ((uint64_t)first_slot + count > S->n_slots) return fail(SVO_EINVAL, "slots [%u, %u) out of range (%u)", first_slot,
+                                                               first_slot + count, S->n_slots);
+    if (count && !fwd_3x4) return fail(SVO_EINVAL, "fwd_3x4 is NULL");
+    std::vector<Aff> keep(S->fwd.begin() + first_slot, S->fwd.begin() + first_slot + count);
+    for (uint32_t j = 0; j < count; ++j) {
+        Aff a;
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 4; ++c) {
+                const float v = fwd_3x4[12 * j + 4 * r + c];
+                if (!std::isfinite(v)) return fail(SVO_EINVAL, "transform of slot %u is not finite", first_slot + j);
+                a.m[r][c] = v;
+            }
+        }
+        Aff inv;
+        if (!aff_inverse(a, inv)) return fail(SVO_EINVAL, "transform of slot %u is singular", first_slot + j);
+        S->fwd[first_slot + j] = a;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int rc = upload_frames(*S, (hipStream_t)stream);
+    if (rc) {
+        std::copy(keep.begin(), keep.end(), S->fwd.begin() + first_slot);
+        return rc;
+    }
+    return SVO_OK;
+}
+
+int svo_get_config(svo_ctx* ctx, svo_config* cfg) {
+    if (!ctx || !cfg) return fail(SVO_EINVAL, "ctx and cfg must not be NULL");
+    *cfg = ctx->cfg;
+    return SVO_OK;
+}
+
+int svo_set_config(svo_ctx* ctx, const svo_config* cfg) {
+    if (!ctx || !cfg) return fail(SVO_EINVAL, "ctx and cfg must not be NULL");
+    svo_config c = *cfg;
+    const svo_config d = default_config();
+    if (!c.waves_per_block) c.waves_per_block = d.waves_per_block;
+    if (!c.blocks_per_cu) c.blocks_per_cu = d.blocks_per_cu;
+    if (!c.step_limit) c.step_limit = d.step_limit;
+    const int rc = check_config(c);
+    if (rc) return rc;
+    ctx->cfg = c;
+    return SVO_OK;
+}
+
+int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                   uint32_t* out_inst, float* out_t, float* out_normal, void* stream) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    Scene* S = find_scene(ctx, scene);
+    if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    if (n == 0) return SVO_OK;
+    if (!rays || !out_id || !out_t) return fail(SVO_EINVAL, "rays, out_id and out_t are required");
+    if (((uintptr_t)rays) & 15u) return fail(SVO_EINVAL, "rays must be 16-byte aligned");
+    if (n > (uint64_t)0xFFFFFFFFu * 64u) return fail(SVO_ERANGE, "too many rays in one call");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t qslot;
+    auto it = ctx->stream_slot.find(st);
+    if (it == ctx->stream_slot.end()) {
+        if (ctx->stream_slot.size() >= kMaxStreams) return fail(SVO_ERANGE, "more than %u streams", kMaxStreams);
+        qslot = (uint32_t)ctx->stream_slot.size();
+        ctx->stream_slot[st] = qslot;
+    } else {
+        qslot = it->second;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    const svo_config& c = ctx->cfg;
+    svo::TraceArgs a{};
+    a.nodes = S->d_nodes;
+    a.frames = S->d_frames[S->cur];
+    a.n_frames = S->n_frames;
+    a.n_cand = S->n_cand;
+    a.rays = reinterpret_cast<const float4*>(rays);
+    a.n_rays = n;
+    a.out_id = out_id;
+    a.out_inst = out_inst;
+    a.out_t = out_t;
+    a.out_n = out_normal;
+    a.queue = ctx->d_queue + 2 * qslot;
+    a.stack_levels = S->stack_levels;
+    a.step_limit = c.step_limit;
+    uint32_t cache = (uint32_t)std::min<uint64_t>(c.lds_cache_nodes, S->n_nodes);
+    size_t lds = svo::trace_lds_bytes(cache, a.n_frames, a.stack_levels, c.waves_per_block);
+    while (lds > ctx->max_lds && cache > 0) {
+        cache /= 2;
+        lds = svo::trace_lds_bytes(cache, a.n_frames, a.stack_levels, c.waves_per_block);
+    }
+    if (lds > ctx->max_lds) return fail(SVO_ERANGE, "scene needs %zu bytes of LDS per work-group", lds);
+    a.lds_nodes = cache;
+    svo::LaunchCfg L{};
+    L.waves_per_block = c.waves_per_block;
+    const uint64_t tiles = (n + 63) / 64;
+    const uint64_t want = (tiles + c.waves_per_block - 1) / c.waves_per_block;
+    const uint64_t cap = (uint64_t)ctx->n_cu * c.blocks_per_cu;
+    L.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+    L.lds_bytes = lds;
+    const hipError_t e = svo::launch_trace(a, L, st);
+    if (e != hipSuccess) return fail(SVO_EDEVICE, "trace launch failed: %s", hipGetErrorString(e));
+    return SVO_OK;
+}
+
+}  // extern "C"

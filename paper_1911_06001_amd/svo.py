@@ -1,0 +1,216 @@
+"""ctypes binding of libsvo.so (the C ABI in include/svo.h).
+
+Argument marshalling only: every step of the trace runs in the library's
+HIP kernels.  torch supplies device memory (``tensor.data_ptr()``) and
+streams (``torch.cuda.current_stream().cuda_stream``).  Importing this
+module raises if the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvo.so")
+
+SVO_OK, SVO_EINVAL, SVO_ENOMEM, SVO_EDEVICE, SVO_ERANGE, SVO_EBUSY, SVO_ESTATE = 0, -1, -2, -3, -4, -5, -6
+NONE = 0xFFFFFFFF
+STEP_LIMIT = 0xFFFFFFFE
+MAX_DEPTH = 20
+MAX_SLOTS = 4096
+MAX_OVERFLOW = 64
+
+# every symbol include/svo.h declares
+EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
+           "svo_free_scene", "svo_scene_bytes", "svo_set_transforms", "svo_trace_rays", "svo_get_config",
+           "svo_set_config")
+
+
+class SvoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("svo error %d: %s" % (code, msg))
+        self.code = code
+
+
+class PoolInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_uint64), ("n_frames", ctypes.c_uint32), ("world_height", ctypes.c_uint32),
+                ("max_height", ctypes.c_uint32), ("max_nesting", ctypes.c_uint32), ("n_shared", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("lds_cache_nodes", ctypes.c_uint32), ("refill_lanes", ctypes.c_uint32),
+                ("step_limit", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Load libsvo.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsvo.so is not built (run paper_1911_06001_amd/build.py or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "svo_abi_version": (I, []),
+        "svo_last_error": (ctypes.c_char_p, []),
+        "svo_create": (I, [ctypes.POINTER(P), I]),
+        "svo_destroy": (None, [P]),
+        "svo_validate": (I, [P, U64, U32, U32, P, U32, ctypes.POINTER(PoolInfo)]),
+        "svo_upload": (I, [P, P, U64, U32, P, ctypes.c_float, U32, P, P, U32, ctypes.POINTER(U32)]),
+        "svo_free_scene": (I, [P, U32]),
+        "svo_scene_bytes": (I, [P, U32, ctypes.POINTER(U64)]),
+        "svo_set_transforms": (I, [P, U32, U32, U32, P, P]),
+        "svo_trace_rays": (I, [P, U32, P, U64, P, P, P, P, P]),
+        "svo_get_config": (I, [P, ctypes.POINTER(Config)]),
+        "svo_set_config": (I, [P, ctypes.POINTER(Config)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().svo_last_error().decode(errors="replace")
+
+
+def _check(rc: int):
+    if rc != SVO_OK:
+        raise SvoError(rc, last_error())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def validate(nodes, root, max_depth, slot_child) -> PoolInfo:
+    """Host-only pool check; returns what it learned, raises SvoError otherwise."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.uint64)
+    sc = np.ascontiguousarray(np.asarray(slot_child, np.uint32).reshape(-1))
+    info = PoolInfo()
+    _check(lib().svo_validate(_np_ptr(nodes), nodes.shape[0], int(root), int(max_depth), _np_ptr(sc), sc.shape[0],
+                              ctypes.byref(info)))
+    return info
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+@dataclass
+class Hits:
+    id: "torch.Tensor"
+    inst: "torch.Tensor"
+    t: "torch.Tensor"
+    normal: "torch.Tensor"
+
+
+class Context:
+    """One device context (svo_create / svo_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self._ptr = ctypes.c_void_p()
+        self.device = int(device)
+        _check(lib().svo_create(ctypes.byref(self._ptr), self.device))
+
+    def close(self):
+        if self._ptr:
+            lib().svo_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- configuration
+    def get_config(self) -> Config:
+        c = Config()
+        _check(lib().svo_get_config(self._ptr, ctypes.byref(c)))
+        return c
+
+    def set_config(self, **kw) -> Config:
+        c = self.get_config()
+        for k, v in kw.items():
+            setattr(c, k, int(v))
+        _check(lib().svo_set_config(self._ptr, ctypes.byref(c)))
+        return self.get_config()
+
+    # -- scenes
+    def upload(self, nodes, root, root_min, root_size, max_depth, slot_child, slot_cell) -> int:
+        nodes = np.ascontiguousarray(nodes, dtype=np.uint64)
+        rmin = np.ascontiguousarray(np.asarray(root_min, np.float32).reshape(3))
+        sc = np.ascontiguousarray(np.asarray(slot_child, np.uint32).reshape(-1))
+        cell = np.ascontiguousarray(np.asarray(slot_cell, np.float32).reshape(-1, 4))
+        h = ctypes.c_uint32(0)
+        _check(lib().svo_upload(self._ptr, _np_ptr(nodes), nodes.shape[0], int(root), _np_ptr(rmin),
+                                float(root_size), int(max_depth), _np_ptr(sc), _np_ptr(cell), sc.shape[0],
+                                ctypes.byref(h)))
+        return int(h.value)
+
+    def upload_scene(self, scene, static: bool = False) -> int:
+        """Upload a generated scene (svogen.scenes.Scene) or its static twin."""
+        nodes = scene.static_nodes if static else scene.nodes
+        return self.upload(nodes, scene.root, scene.root_min, scene.root_size, scene.max_depth, scene.slot_child,
+                           scene.slot_cell)
+
+    def free_scene(self, scene: int):
+        _check(lib().svo_free_scene(self._ptr, int(scene)))
+
+    def scene_bytes(self, scene: int) -> int:
+        b = ctypes.c_uint64(0)
+        _check(lib().svo_scene_bytes(self._ptr, int(scene), ctypes.byref(b)))
+        return int(b.value)
+
+    def set_transforms(self, scene: int, fwd, first: int = 0, stream=None):
+        f = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
+        _check(lib().svo_set_transforms(self._ptr, int(scene), int(first), f.shape[0], _np_ptr(f),
+                                        _stream_handle(stream)))
+
+    def trace_into(self, scene: int, rays, out_id, out_t, out_inst=None, out_normal=None, stream=None):
+        """Trace device rays [n, 8] float32 into preallocated device outputs."""
+        n = rays.shape[0]
+        _check(lib().svo_trace_rays(self._ptr, int(scene), rays.data_ptr(), n, out_id.data_ptr(),
+                                    None if out_inst is None else out_inst.data_ptr(), out_t.data_ptr(),
+                                    None if out_normal is None else out_normal.data_ptr(), _stream_handle(stream)))
+
+    def trace(self, scene: int, rays, stream=None, normals: bool = True) -> Hits:
+        import torch
+        if not rays.is_cuda or rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8:
+            raise ValueError("rays must be a float32 device tensor of shape [n, 8]")
+        rays = rays.contiguous()
+        n = rays.shape[0]
+        dev = rays.device
+        out_id = torch.empty(n, dtype=torch.int32, device=dev)
+        out_inst = torch.empty(n, dtype=torch.int32, device=dev)
+        out_t = torch.empty(n, dtype=torch.float32, device=dev)
+        out_n = torch.empty((n, 3), dtype=torch.float32, device=dev) if normals else None
+        self.trace_into(scene, rays, out_id, out_t, out_inst, out_n, stream)
+        return Hits(out_id, out_inst, out_t, out_n)

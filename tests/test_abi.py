@@ -1,0 +1,102 @@
+"""The C ABI on the host (no GPU): the library loads, exports every symbol
+include/svo.h declares, and its pool validation accepts generated pools and
+rejects malformed ones with SVO_EINVAL / SVO_ERANGE."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1911_06001_amd import svo
+from svogen import octree as ot
+from svogen import scenes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NONE = 0xFFFFFFFF
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "svo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(svo_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = svo.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(svo.EXPORTS)
+    assert L.svo_abi_version() == 1
+
+
+def test_create_fails_cleanly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(svo.SvoError) as e:
+        svo.Context(0)
+    assert e.value.code == svo.SVO_EDEVICE
+
+
+def test_validate_generated_pools():
+    sc = S.config1()
+    info = svo.validate(sc.nodes, sc.root, sc.max_depth, sc.slot_child)
+    assert info.n_nodes == sc.nodes.shape[0]
+    assert info.n_frames == 2 and info.world_height == 6 and info.max_nesting == 1
+    t = S.tiny_scene(3, K=5, n_slots=4, nested=True)
+    info = svo.validate(t.nodes, t.root, t.max_depth, t.slot_child)
+    assert info.n_frames == 5 and info.max_nesting >= 2
+    info = svo.validate(t.static_nodes, t.root, t.max_depth, t.slot_child)
+    assert info.n_frames == 1
+    info = svo.validate(ot.force_far(t.nodes), t.root, t.max_depth, t.slot_child)
+    assert info.n_frames == 5
+    info = svo.validate(np.zeros(0, np.uint64), NONE, 4, np.zeros(0, np.uint32))
+    assert info.n_frames == 1 and info.world_height == 0
+
+
+def _expect(code, nodes, root=0, max_depth=8, slot_child=()):
+    with pytest.raises(svo.SvoError) as e:
+        svo.validate(np.asarray(nodes, np.uint64), root, max_depth, np.asarray(slot_child, np.uint32))
+    assert e.value.code == code, str(e.value)
+
+
+def _n(mask, c24=0, w1=0):
+    return np.uint64(mask) | (np.uint64(c24) << np.uint64(8)) | (np.uint64(w1) << np.uint64(32))
+
+
+LEAF = _n(0, 0, 0xFF00FF00)
+
+
+def test_validate_rejects_malformed_pools():
+    _expect(svo.SVO_EINVAL, [_n(0b11, 1), LEAF])                 # group of two runs off the pool
+    _expect(svo.SVO_EINVAL, [_n(1, 0), LEAF])                     # c24 == 0
+    _expect(svo.SVO_EINVAL, [_n(1, 1, 5), LEAF])                  # word1 set on a relative node
+    _expect(svo.SVO_EINVAL, [_n(1, 0xFFFFFF, 7), LEAF])           # far pointer out of range
+    _expect(svo.SVO_EINVAL, [_n(1, 0xFFFFFF, 0)])                 # far pointer to itself: cycle
+    _expect(svo.SVO_EINVAL, [_n(1, 1), _n(1, 0xFFFFFF, 0)])       # 2-cycle
+    _expect(svo.SVO_EINVAL, [_n(1, 1), _n(1, 0, 0x80000000 | 3), LEAF], slot_child=[2])   # slot out of range
+    _expect(svo.SVO_EINVAL, [_n(1, 0, 0x80000000), LEAF], slot_child=[1])                 # transformed root
+    _expect(svo.SVO_EINVAL, [LEAF], root=1)                                                # root out of range
+    # one slot used by two nodes
+    _expect(svo.SVO_EINVAL, [_n(0b11, 1), _n(1, 0, 0x80000000), _n(1, 0, 0x80000000), LEAF], slot_child=[3])
+    # a shared subtree (both children point at node 3) containing a transformed node
+    pool = [_n(0b11, 1), _n(1, 0xFFFFFF, 3), _n(1, 0xFFFFFF, 3), _n(1, 0, 0x80000000), LEAF]
+    _expect(svo.SVO_EINVAL, pool, slot_child=[4])
+    # the same sharing without a transform is fine
+    ok = [_n(0b11, 1), _n(1, 0xFFFFFF, 3), _n(1, 0xFFFFFF, 3), _n(1, 1), LEAF]
+    info = svo.validate(np.asarray(ok, np.uint64), 0, 8, np.zeros(0, np.uint32))
+    assert info.n_shared == 1
+    # depth limits
+    chain = [_n(1, 1) for _ in range(6)] + [LEAF]
+    _expect(svo.SVO_ERANGE, chain, max_depth=5)
+    svo.validate(np.asarray(chain, np.uint64), 0, 6, np.zeros(0, np.uint32))
+    _expect(svo.SVO_ERANGE, chain, max_depth=21)
+
+
+def test_validate_instancing_shares_slot_children():
+    # two transformed nodes (slots 0 and 1) share one child group: allowed
+    pool = [_n(0b11, 1), _n(1, 0, 0x80000000 | 0), _n(1, 0, 0x80000000 | 1), LEAF]
+    info = svo.validate(np.asarray(pool, np.uint64), 0, 8, np.asarray([3, 3], np.uint32))
+    assert info.n_frames == 3 and info.n_shared == 1
