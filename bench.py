@@ -1,0 +1,216 @@
+"""Benchmark: animated vs static SVO trace at 1080p on one MI355X.
+
+Workload: depth-10 (1024^3) fBm heightfield, 8 level-3 subtrees
+animated per frame (rotation + anisotropic scale 0.5..2), 1920x1080 primary
+rays.  One step = one frame: upload that frame's transforms
+(svo_set_transforms: FP64 compose/invert + 64-byte records) and trace all
+2,073,600 rays (svo_trace_rays), rays and pool resident in HBM.  The static
+twin (same pool, no transforms, same rays) is timed the same way.
+
+Prints one JSON line.  value = animated Mrays/s over the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s animated vs static SVO trace at 1080p; p50/p99 served frame latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1911_06001_amd/csrc/svo_trace.hip", "paper_1911_06001_amd/csrc/svo_internal.h"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_kernel_terrain1024_1080p_pmc.txt")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(launch_rays: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(scene, rays, frames, budget_s):
+    """The oracle as it stands, on the host cores, over whole frames of the
+    same workload until ``budget_s`` seconds have been spent."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    done = 0
+    spent = 0.0
+    bytes_sum = 0.0
+    frame_list = []
+    f = 0
+    while spent < budget_s and f < frames:
+        t0 = time.perf_counter()
+        h = oracle.trace_scene(scene, rays, frame=f, counters=True, nthreads=threads)
+        spent += time.perf_counter() - t0
+        done += rays.shape[0]
+        # algorithmic bytes per ray: 8 B per node record, 64 B per frame
+        # record, 32 B ray in, 24 B hit out
+        bytes_sum += float((8.0 * h.nnode.astype(np.float64) + 64.0 * h.nframe + 32.0 + 24.0).sum())
+        frame_list.append(f)
+        f += 1
+    return dict(rays=done, seconds=spent, threads=threads, frames=frame_list, bytes_per_ray=bytes_sum / max(done, 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=60, help="animation cycle length")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle budget (0 disables)")
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how rays "
+              "would shard); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_06001_amd import svo
+    from svogen import scenes
+
+    t0 = time.perf_counter()
+    sc = scenes.fbm_terrain_d10(frames=args.frames)
+    rays_np, _ = sc.rays(W=args.width, H=args.height)
+    n = rays_np.shape[0]
+    log("scene: %d nodes, %d slots, %d rays (%.1f s)" % (sc.nodes.shape[0], sc.n_slots, n, time.perf_counter() - t0))
+
+    dev = torch.device("cuda:0")
+    rays = torch.from_numpy(rays_np).to(dev)
+    out_id = torch.empty(n, dtype=torch.int32, device=dev)
+    out_inst = torch.empty(n, dtype=torch.int32, device=dev)
+    out_t = torch.empty(n, dtype=torch.float32, device=dev)
+    out_n = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    ctx = svo.Context(0)
+    anim = ctx.upload_scene(sc)
+    stat = ctx.upload_scene(sc, static=True)
+    xf = [sc.xform(f) for f in range(args.frames)]
+    stream = torch.cuda.current_stream()
+
+    def step_anim(k):
+        ctx.set_transforms(anim, xf[k % args.frames], stream=stream)
+        ctx.trace_into(anim, rays, out_id, out_t, out_inst, out_n, stream=stream)
+
+    def step_static(k):
+        ctx.trace_into(stat, rays, out_id, out_t, out_inst, out_n, stream=stream)
+
+    def timed(step, K):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for k in range(K):
+            if step is step_anim:
+                ctx.set_transforms(anim, xf[k % args.frames], stream=stream)
+                evs[k][0].record(stream)
+                ctx.trace_into(anim, rays, out_id, out_t, out_inst, out_n, stream=stream)
+                evs[k][1].record(stream)
+            else:
+                evs[k][0].record(stream)
+                ctx.trace_into(stat, rays, out_id, out_t, out_inst, out_n, stream=stream)
+                evs[k][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        kms = [a.elapsed_time(b) for a, b in evs]
+        return wall, kms
+
+    for k in range(args.warmup):
+        step_anim(k)
+        step_static(k)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    K = args.steps
+    wall_a, kms_a = timed(step_anim, K)
+    log("animated: %.3f ms/step wall, kernel mean %.3f ms" % (wall_a / K * 1e3, float(np.mean(kms_a))))
+    wall_s, kms_s = timed(step_static, K)
+    log("static: %.3f ms/step wall, kernel mean %.3f ms" % (wall_s / K * 1e3, float(np.mean(kms_s))))
+
+    value = n * K / wall_a / 1e6
+    static_value = n * K / wall_s / 1e6
+    kmean_a = float(np.mean(kms_a)) * 1e-3
+
+    cpu = None
+    bytes_per_ray = None
+    if args.cpu_seconds > 0:
+        log("oracle baseline on host cores (budget %.0f s)" % args.cpu_seconds)
+        cb = cpu_baseline(sc, rays_np, args.frames, args.cpu_seconds)
+        bytes_per_ray = cb["bytes_per_ray"]
+        cpu = {"value": round(cb["rays"] / cb["seconds"] / 1e6, 4), "unit": "Mrays/s", "cores": cb["threads"],
+               "kind": "oracle",
+               "sample": "animated terrain1024 frames %d..%d, all %d rays each (%d rays, %.1f s)" % (
+                   cb["frames"][0], cb["frames"][-1], n, cb["rays"], cb["seconds"])}
+    roof = None
+    if bytes_per_ray is not None:
+        achieved = bytes_per_ray * n / kmean_a / 1e9
+        traffic = read_traffic(n)
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "bytes_per_ray": round(bytes_per_ray, 2), "rays_per_launch": n,
+                "kernel_ms": round(kmean_a * 1e3, 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_a / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "terrain1024: depth-10 (1024^3) fBm heightfield SVO, 8 level-3 subtrees animated per "
+                               "frame (rotation + anisotropic scale 0.5-2), %dx%d primary rays, %d-frame cycle"
+                               % (args.width, args.height, args.frames),
+                   "rays_per_step": n, "nodes": int(sc.nodes.shape[0]), "slots": sc.n_slots},
+        "static": {"value": round(static_value, 3), "unit": "Mrays/s", "ms_per_step": round(wall_s / K * 1e3, 4),
+                   "kernel_ms": round(float(np.mean(kms_s)), 4)},
+        "animated_over_static_time": round(wall_a / wall_s, 4),
+        "animated_over_static_kernel_time": round(float(np.mean(kms_a)) / float(np.mean(kms_s)), 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    ctx.free_scene(anim)
+    ctx.free_scene(stat)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,9 +4,9 @@ Every scene is a pool of 8-byte nodes plus a slot table (child group and
 local root cell of every transformed subtree) and a function giving the
 forward, parent-relative 3x4 transform of every slot at a given frame.
 
-  config1  depth 6 (64^3) noisy sphere, one transformed level-1 node,
+  noisy_sphere_d6   depth 6 (64^3) noisy sphere, one transformed level-1 node,
            128x128 pinhole rays                          (small parity case)
-  config2  depth 10 (1024^3) fBm heightfield, 8 animated level-3 subtrees,
+  fbm_terrain_d10   depth 10 (1024^3) fBm heightfield, 8 animated level-3 subtrees,
            1920x1080 pinhole rays, 60 frames           (headline workload)
   tiny     depth 3..5 random blobs with random nested transforms (pins)
 
@@ -132,9 +132,9 @@ def _marked_scene(name, tree, K, root_size, cells, xform, camera, seed):
                  camera=camera, seed=seed)
 
 
-# ------------------------------------------------------------------ config 1
+# ------------------------------------------------------------------ noisy sphere, depth 6
 
-def config1(seed: int = 1) -> Scene:
+def noisy_sphere_d6(seed: int = 1) -> Scene:
     """Depth-6 noisy sphere; slot 0 on the level-1 node of octant 7 ([32,64)^3)
     rotated +30 deg about y through its centre (48,48,48), then moved (5,0,2)."""
     K = 6
@@ -152,10 +152,10 @@ def config1(seed: int = 1) -> Scene:
         return A32.copy()
 
     camera = dict(eye=(112.0, 96.0, 128.0), target=(32.0, 32.0, 32.0), up=(0.0, 1.0, 0.0), fov=45.0, W=128, H=128)
-    return _marked_scene("config1", tree, K, float(n), [(1, (1, 1, 1))], xform, camera, seed)
+    return _marked_scene("sphere64", tree, K, float(n), [(1, (1, 1, 1))], xform, camera, seed)
 
 
-# ------------------------------------------------------------------ config 2
+# ------------------------------------------------------------------ fBm terrain, depth 10
 
 def heightfield(K: int, seed: int, base: float, amp: float, octaves: int, period0: float):
     n = 1 << K
@@ -165,7 +165,7 @@ def heightfield(K: int, seed: int, base: float, amp: float, octaves: int, period
     return np.clip(np.ceil(h - 0.5), 0, n).astype(np.int64)
 
 
-def config2(seed: int = 2, frames: int = 60) -> Scene:
+def fbm_terrain_d10(seed: int = 2, frames: int = 60) -> Scene:
     """Depth-10 fBm heightfield h = 512 + 256 fbm2 (6 octaves, P0 = 256); 8
     level-3 subtrees animated: rotation about a seeded axis by 2 pi k f/60
     (k in {1,2,3}) and per-axis scale 2^sin(2 pi f/60 + phase) about the cell
@@ -200,7 +200,7 @@ def config2(seed: int = 2, frames: int = 60) -> Scene:
 
     camera = dict(eye=(512.0, 1100.0, -400.0), target=(512.0, 500.0, 512.0), up=(0.0, 1.0, 0.0),
                   fov=60.0, W=1920, H=1080)
-    return _marked_scene("config2", tree, K, float(1 << K), cells, xform, camera, seed)
+    return _marked_scene("terrain1024", tree, K, float(1 << K), cells, xform, camera, seed)
 
 
 # ------------------------------------------------------------------ tiny scenes for pins

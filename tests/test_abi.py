@@ -41,7 +41,7 @@ def test_create_fails_cleanly_without_device():
 
 
 def test_validate_generated_pools():
-    sc = S.config1()
+    sc = S.noisy_sphere_d6()
     info = svo.validate(sc.nodes, sc.root, sc.max_depth, sc.slot_child)
     assert info.n_nodes == sc.nodes.shape[0]
     assert info.n_frames == 2 and info.world_height == 6 and info.max_nesting == 1

@@ -60,26 +60,26 @@ def _check_scene(ctx, torch, sc, rays, frame=0, static=False, fwd=None, max_rate
     return st
 
 
-def test_config1_full(ctx, torch_dev):
-    sc = S.config1()
+def test_sphere64_full(ctx, torch_dev):
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays()
-    st = _check_scene(ctx, torch_dev, sc, rays, max_rate=1e-4, label="config1")
+    st = _check_scene(ctx, torch_dev, sc, rays, max_rate=1e-4, label="sphere64")
     assert st["hits"] > 2000
 
 
-def test_config1_static_and_identity(ctx, torch_dev):
-    sc = S.config1()
+def test_sphere64_static_and_identity(ctx, torch_dev):
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays()
-    _check_scene(ctx, torch_dev, sc, rays, static=True, max_rate=1e-4, label="config1-static")
+    _check_scene(ctx, torch_dev, sc, rays, static=True, max_rate=1e-4, label="sphere64-static")
     ident = xf.to_f32(xf.identity()).reshape(1, 12)
-    _check_scene(ctx, torch_dev, sc, rays, fwd=ident, max_rate=1e-4, label="config1-identity")
+    _check_scene(ctx, torch_dev, sc, rays, fwd=ident, max_rate=1e-4, label="sphere64-identity")
 
 
-def test_config1_rows_order_and_ragged(ctx, torch_dev):
-    sc = S.config1()
+def test_sphere64_rows_order_and_ragged(ctx, torch_dev):
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays(order="rows")
     for n in (1, 63, 64, 65, 1000, 4097):
-        _check_scene(ctx, torch_dev, sc, rays[:n], label="config1-ragged-%d" % n)
+        _check_scene(ctx, torch_dev, sc, rays[:n], label="sphere64-ragged-%d" % n)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6])
@@ -103,18 +103,18 @@ def test_axis_aligned_and_inside(ctx, torch_dev):
     _check_scene(ctx, torch_dev, sc, np.array(rays, np.float32), label="axis-aligned")
 
 
-def test_config2_reduced_frames(ctx, torch_dev):
-    sc = S.config2()
+def test_terrain1024_reduced_frames(ctx, torch_dev):
+    sc = S.fbm_terrain_d10()
     rays, _ = sc.rays(W=320, H=180)
     for f in (0, 17, 45):
-        _check_scene(ctx, torch_dev, sc, rays, frame=f, max_rate=1e-4, label="config2-320x180-f%d" % f)
-    _check_scene(ctx, torch_dev, sc, rays, static=True, max_rate=1e-4, label="config2-320x180-static")
+        _check_scene(ctx, torch_dev, sc, rays, frame=f, max_rate=1e-4, label="terrain1024-320x180-f%d" % f)
+    _check_scene(ctx, torch_dev, sc, rays, static=True, max_rate=1e-4, label="terrain1024-320x180-static")
 
 
-def test_config2_full_resolution_sampled(ctx, torch_dev):
+def test_terrain1024_full_resolution_sampled(ctx, torch_dev):
     """1920x1080 in the benchmark's launch: every 17th ray plus one 64x64 tile
     block of rays are checked against the oracle one by one."""
-    sc = S.config2()
+    sc = S.fbm_terrain_d10()
     rays, pix = sc.rays()
     n = rays.shape[0]
     idx = np.unique(np.concatenate([np.arange(0, n, 17), np.arange(400 * 64, 400 * 64 + 4096)]))
@@ -126,7 +126,7 @@ def test_config2_full_resolution_sampled(ctx, torch_dev):
         ctx.free_scene(h)
     ref = oracle.trace_scene(sc, rays[idx], frame=30, margin=True)
     st = parity.compare(tuple(a[idx] for a in g), ref, ref.margin)
-    _say("config2-1080p-sampled", st)
+    _say("terrain1024-1080p-sampled", st)
     parity.assert_parity(st, 1e-4)
 
 
@@ -185,7 +185,7 @@ def test_degenerate_rays_and_worlds(ctx, torch_dev):
 
 def test_zero_rays_and_repeated_launches(ctx, torch_dev):
     torch = torch_dev
-    sc = S.config1()
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays()
     h = ctx.upload_scene(sc)
     try:
@@ -208,7 +208,7 @@ def test_zero_rays_and_repeated_launches(ctx, torch_dev):
 
 def test_transform_updates_are_stream_ordered(ctx, torch_dev):
     torch = torch_dev
-    sc = S.config2()
+    sc = S.fbm_terrain_d10()
     rays, _ = sc.rays(W=160, H=90)
     r = torch.from_numpy(rays).cuda()
     h = ctx.upload_scene(sc)

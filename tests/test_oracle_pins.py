@@ -67,8 +67,8 @@ def test_p1_axis_aligned_and_inside_rays(oracle_lib):
     np.testing.assert_allclose(h.normal[ok], bn[ok], atol=1e-9)
 
 
-def test_p1_config1(oracle_lib):
-    sc = S.config1()
+def test_p1_noisy_sphere_d6(oracle_lib):
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays(W=48, H=48)
     h = oracle.trace_scene(sc, rays, margin=True)
     bid, binst, bt, bn = bf.trace(sc, sc.xform(0), rays)
@@ -111,8 +111,8 @@ def test_p2_identity_equals_static(seed, oracle_lib):
     assert (ha.inst[ok & (ha.id != NONE)] != NONE).any()
 
 
-def test_p2_config1_identity(oracle_lib):
-    sc = S.config1()
+def test_p2_sphere64_identity(oracle_lib):
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays()
     ident = xf.to_f32(xf.identity()).reshape(1, 12)
     ha = oracle.trace_scene(sc, rays, fwd=ident, margin=True)
@@ -349,7 +349,7 @@ def test_p6_voxelised_sphere_bounds(oracle_lib):
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
     occ = np.sqrt((X - 32) ** 2 + (Y - 32) ** 2 + (Z - 32) ** 2) < R
     tree = ot.build_tree(K, ot.dense_classifier(occ)[0])
-    sc = S.config1()
+    sc = S.noisy_sphere_d6()
     rays, _ = sc.rays(W=96, H=96)
     h = oracle.trace(tree.nodes, 0, np.zeros(3), float(n), np.zeros(0, np.uint32), np.zeros((0, 4)), np.zeros((0, 12)), rays)
     o = rays[:, :3].astype(np.float64)
