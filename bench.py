@@ -91,7 +91,24 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle budget (0 disables)")
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--lds-cache-nodes", type=int, default=-1)
+    ap.add_argument("--refill", type=int, default=-1)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 5}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -116,6 +133,17 @@ def main():
     out_t = torch.empty(n, dtype=torch.float32, device=dev)
     out_n = torch.empty((n, 3), dtype=torch.float32, device=dev)
     ctx = svo.Context(0)
+    knobs = {}
+    if args.waves_per_block:
+        knobs["waves_per_block"] = args.waves_per_block
+    if args.blocks_per_cu:
+        knobs["blocks_per_cu"] = args.blocks_per_cu
+    if args.lds_cache_nodes >= 0:
+        knobs["lds_cache_nodes"] = args.lds_cache_nodes
+    if args.refill >= 0:
+        knobs["refill_lanes"] = args.refill
+    cfg = ctx.set_config(**knobs).as_dict()
+    log("kernel config", cfg)
     anim = ctx.upload_scene(sc)
     stat = ctx.upload_scene(sc, static=True)
     xf = [sc.xform(f) for f in range(args.frames)]
@@ -198,7 +226,7 @@ def main():
         "config": {"workload": "terrain1024: depth-10 (1024^3) fBm heightfield SVO, 8 level-3 subtrees animated per "
                                "frame (rotation + anisotropic scale 0.5-2), %dx%d primary rays, %d-frame cycle"
                                % (args.width, args.height, args.frames),
-                   "rays_per_step": n, "nodes": int(sc.nodes.shape[0]), "slots": sc.n_slots},
+                   "rays_per_step": n, "nodes": int(sc.nodes.shape[0]), "slots": sc.n_slots, "kernel": cfg},
         "static": {"value": round(static_value, 3), "unit": "Mrays/s", "ms_per_step": round(wall_s / K * 1e3, 4),
                    "kernel_ms": round(float(np.mean(kms_s)), 4)},
         "animated_over_static_time": round(wall_a / wall_s, 4),

@@ -85,8 +85,8 @@ typedef enum {
 #define SVO_NONE 0xFFFFFFFFu        /* miss id / inst; world frame; empty world root */
 #define SVO_STEP_LIMIT 0xFFFFFFFEu  /* id of a ray that exceeded the per-ray step limit */
 #define SVO_MAX_DEPTH 20u           /* levels below any frame root */
-#define SVO_MAX_SLOTS 4096u         /* transform slots per scene */
-#define SVO_MAX_OVERFLOW 64u        /* slots per scene whose moved content leaves its static cell */
+#define SVO_MAX_SLOTS 1023u         /* transform slots per scene (all frame records live in LDS) */
+#define SVO_MAX_INLINE_NEST 4u      /* slots entered in place may nest this deep */
 
 typedef struct svo_ctx svo_ctx;     /* opaque: device, pools, transform tables, work queues */
 typedef uint32_t svo_scene;         /* scene handle, 0 is never valid */
@@ -102,13 +102,24 @@ typedef struct {
     uint32_t reserved;
 } svo_pool_info;
 
+/* How the current transforms classify a scene's frames (svo_get_scene_stats). */
+typedef struct {
+    uint64_t device_bytes;    /* pool + transform tables */
+    uint32_t n_slots;
+    uint32_t n_frames;        /* 1 (world) + referenced slots */
+    uint32_t n_inline;        /* slots entered in place by the walk */
+    uint32_t n_candidates;    /* slots traced from their own roots */
+    uint32_t stack_levels;    /* traversal stack entries per lane */
+    uint32_t nest_levels;     /* deepest chain of in-place frames */
+} svo_scene_stats;
+
 /* Kernel configuration; svo_tune() picks one, svo_set_config() sets one.
    Zero fields select the library defaults. */
 typedef struct {
     uint32_t waves_per_block;   /* 1..16 wavefronts (64 lanes) per work-group */
     uint32_t blocks_per_cu;     /* resident work-groups per compute unit for the persistent grid */
     uint32_t lds_cache_nodes;   /* first N pool nodes (the top levels, breadth-first) kept in LDS */
-    uint32_t refill_lanes;      /* 0: a wave takes 64-ray tiles; k>0: refill once >= k lanes are idle */
+    uint32_t refill_lanes;      /* 0 or 64: a wave takes 64-ray tiles; 1..63: claim new rays once that many lanes are idle */
     uint32_t step_limit;        /* node steps per ray before SVO_STEP_LIMIT */
     uint32_t reserved[3];
 } svo_config;
@@ -153,15 +164,20 @@ int svo_free_scene(svo_ctx* ctx, svo_scene scene);
 /* Device bytes the scene holds (pool + transform tables), for admission. */
 int svo_scene_bytes(svo_ctx* ctx, svo_scene scene, uint64_t* bytes);
 
+/* Classification of the scene's frames under its latest transforms. */
+int svo_get_scene_stats(svo_ctx* ctx, svo_scene scene, svo_scene_stats* out);
+
 /* Set the parent-relative forward maps of slots [first_slot, first_slot +
    count).  fwd_3x4: host, count * 12 floats, row-major 3x4 [L | b] with
    x_parent = L x_local + b (paper Eq. 3 inverts this per frame; nested slots
    compose).  The library composes and inverts in FP64 on the host, packs one
    64-byte FP32 record per frame and copies the whole table on `stream`;
    traces enqueued on `stream` afterwards see the new transforms, earlier
-   ones the old (two device tables alternate).  SVO_EINVAL on a non-finite
-   or singular map, on slots out of range, or when more than
-   SVO_MAX_OVERFLOW slots leave their static cell. */
+   ones the old (two device tables alternate).  A slot whose moved cell stays
+   inside its static cell (with a margin of 1e-5 cell) is entered in place
+   when the walk reaches it (at most SVO_MAX_INLINE_NEST deep); every other
+   slot is traced as a separate candidate in order of its root-cell entry.
+   SVO_EINVAL on a non-finite or singular map or slots out of range. */
 int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint32_t count, const float* fwd_3x4,
                        void* stream);
 
@@ -175,9 +191,73 @@ int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint3
 int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                    uint32_t* out_inst, float* out_t, float* out_normal, void* stream);
 
-/* Current kernel configuration of the context / replace it (validated). */
+/* One job of a batched launch: rays traced against one scene under one set
+   of transforms. */
+typedef struct {
+    svo_scene scene;
+    const float* fwd_3x4;     /* host, n_slots * 12 floats (every slot of the scene, parent-relative,
+                                 as in svo_set_transforms), or NULL for the scene's current transforms */
+    const float* rays;        /* device, n * 8 floats, 16-byte aligned */
+    uint64_t n;
+    uint32_t* out_id;         /* device outputs, as in svo_trace_rays */
+    uint32_t* out_inst;       /* nullable */
+    float* out_t;
+    float* out_normal;        /* nullable */
+} svo_job;
+
+/* Trace several jobs -- rays of many requests, scenes and animation frames
+   -- in one persistent launch: the work queue spans every job's rays, each
+   ray walks its own job's scene under its own transforms (one pixel/ray as in
+   the paper's per-pixel algorithm, Fig. 5).  Results are identical to one
+   svo_trace_rays per job.  At most 256 non-empty jobs and 2047 frame
+   records (1 + n_slots per job) per call; jobs with n == 0 are skipped.  The
+   job table is packed on the host into pinned memory and copied on `stream`
+   (a ring of four tables; a fifth call waits for the first to finish). */
+int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
+
+/* Current kernel configuration of the context / replace it (validated).
+   svo_set_config also drops every scene's tuned configuration. */
 int svo_get_config(svo_ctx* ctx, svo_config* cfg);
 int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
+
+/* Autotuner.  Times candidate kernel configurations (waves per work-group,
+   resident work-groups per CU, LDS pool-prefix size, lane refill) on n
+   device sample rays against `scene` under its current transforms, keeps
+   the fastest for that scene -- later svo_trace_rays calls on it use it, and
+   a batch uses it when that scene holds most of the batch's rays -- and
+   writes it to *best (nullable).  Results never depend on the
+   configuration, only speed does.  Allocates and frees its own scratch
+   outputs and synchronises `stream`; not for use inside a timed loop. */
+int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n, void* stream, svo_config* best);
+
+/* Pinhole camera for svo_generate_primary_rays.  forward, right and up are
+   unit vectors (right = forward x up); pixel (i, j), j counted from the top
+   row, sample s has direction normalize(forward + sx right + sy up) with
+   sx = ((i + fx) / width * 2 - 1) tan_half_fov * width / height and
+   sy = (1 - (j + fy) / height * 2) tan_half_fov, where (fx, fy) = (1/2, 1/2)
+   unless jitter is set, in which case they are hashed from (seed, pixel,
+   sample) into [0, 1). */
+typedef struct {
+    float eye[3];
+    float forward[3];
+    float right[3];
+    float up[3];
+    float tan_half_fov;
+    uint32_t width, height;
+    uint32_t samples;         /* rays per pixel, >= 1 */
+    uint32_t seed;
+    uint32_t jitter;          /* 0: pixel centres */
+    uint32_t tiled;           /* 1: 8x8 pixel tiles (see below), 0: rows */
+    uint32_t reserved;
+} svo_camera;
+
+/* Write width * height * samples primary rays (8 floats each, tmin = 0,
+   tmax = +inf) to out_rays (device, 16-byte aligned) on `stream`.  Order:
+   tiled -- 8x8 pixel tiles, tile rows top to bottom, tiles left to right,
+   pixels row-major inside a tile, partial edge tiles holding only in-image
+   pixels; otherwise row-major pixels.  The samples of one pixel are
+   consecutive. */
+int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream);
 
 #ifdef __cplusplus
 }

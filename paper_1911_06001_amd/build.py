@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsvo.so")
-SOURCES = [os.path.join(HERE, "csrc", "svo_host.cpp"), os.path.join(HERE, "csrc", "svo_trace.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "svo_host.cpp"), os.path.join(HERE, "csrc", "svo_trace.hip"),
+           os.path.join(HERE, "csrc", "svo_raygen.hip")]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # keep hipcc from emitting packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

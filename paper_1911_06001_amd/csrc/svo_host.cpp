@@ -291,14 +291,17 @@ struct Scene {
     uint32_t world_child = 0;
     uint32_t world_mask = 0;
     uint64_t* d_nodes = nullptr;
-    svo::FrameRec* d_frames[2] = {nullptr, nullptr};
-    svo::FrameRec* h_stage[2] = {nullptr, nullptr};
+    unsigned char* d_table[2] = {nullptr, nullptr};   // frame records, then the candidate list
+    unsigned char* h_stage[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
+    size_t table_bytes = 0;
     int cur = 0;                        // table the next trace reads
-    uint32_t n_frames = 1;              // records in the current table
-    uint32_t n_cand = 0;
-    uint32_t stack_levels = 1;
+    uint32_t n_frames = 1;              // 1 + n_slots records per table
+    // classification of the current table
+    uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0;
     uint64_t bytes = 0;
+    bool tuned = false;                 // svo_tune picked `cfg` for this scene
+    svo_config cfg{};
 };
 
 }  // namespace
@@ -312,6 +315,16 @@ struct svo_ctx {
     std::map<uint32_t, std::unique_ptr<Scene>> scenes;
     uint32_t* d_queue = nullptr;                // kMaxStreams pairs of counters
     std::map<hipStream_t, uint32_t> stream_slot;
+    // ring of batch tables (job records, frames, candidates): pinned staging
+    // + device copy, reused once the launch that read them has finished
+    struct BatchBuf {
+        unsigned char* dev = nullptr;
+        unsigned char* host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+    };
+    BatchBuf batch[4];
+    uint32_t next_batch = 0;
 };
 
 namespace {
@@ -337,7 +350,7 @@ int check_config(const svo_config& c) {
 void free_scene(Scene& s) {
     if (s.d_nodes) (void)hipFree(s.d_nodes);
     for (int k = 0; k < 2; ++k) {
-        if (s.d_frames[k]) (void)hipFree(s.d_frames[k]);
+        if (s.d_table[k]) (void)hipFree(s.d_table[k]);
         if (s.h_stage[k]) (void)hipHostFree(s.h_stage[k]);
         if (s.ev[k]) (void)hipEventDestroy(s.ev[k]);
     }
@@ -349,13 +362,23 @@ Scene* find_scene(svo_ctx* ctx, svo_scene h) {
     return it == ctx->scenes.end() ? nullptr : it->second.get();
 }
 
-// Compose, invert and pack the frame table into `out` (host).  Frames:
-// [0] world, then every referenced slot (all are candidates for now).
-int build_frames(Scene& S, svo::FrameRec* out, uint32_t& n_frames, uint32_t& n_cand) {
+struct TableInfo {
+    uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0;
+};
+
+// Compose, invert and pack the frame table into `out` (host): record 0 is
+// the world, record 1 + s slot s; the candidate list follows the records.
+// A slot whose moved cell stays inside its static cell is entered in place
+// (FR_INLINE, nesting bounded by kMaxInlineNest); every other referenced slot
+// is a candidate traced from its own root.
+int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out, TableInfo& T) {
     const Analysis& A = S.an;
+    svo::FrameRec* rec = reinterpret_cast<svo::FrameRec*>(out);
+    uint32_t* cand = reinterpret_cast<uint32_t*>(out + (size_t)S.n_frames * sizeof(svo::FrameRec));
+    std::memset(out, 0, S.table_bytes);
+    T = TableInfo();
     // world
-    svo::FrameRec& W = out[0];
-    std::memset(&W, 0, sizeof W);
+    svo::FrameRec& W = rec[0];
     const uint32_t K0 = A.world_height;
     const double g0 = std::ldexp(1.0, (int)K0) / (double)S.root_size;
     for (int r = 0; r < 3; ++r) {
@@ -367,25 +390,27 @@ int build_frames(Scene& S, svo::FrameRec* out, uint32_t& n_frames, uint32_t& n_c
     if (S.root == SVO_NONE) {
         W.info = svo::FR_EMPTY;
     } else {
-        W.info = (K0 << svo::FR_K_SHIFT);
+        W.info = (K0 << svo::FR_K_SHIFT) | S.world_mask;
         if (K0 == 0) W.info |= svo::FR_ROOT_LEAF;
         W.child = S.world_child;
-        W.info |= S.world_mask;
     }
-    n_frames = 1;
+    T.stack_levels = std::max<uint32_t>(T.stack_levels, K0 + 1);
+    for (uint32_t s = 0; s < S.n_slots; ++s) {
+        rec[1 + s].info = svo::FR_EMPTY;
+        rec[1 + s].inst = s;
+        rec[1 + s].root = SVO_NONE;
+    }
     std::vector<Aff> world(S.n_slots);
+    std::vector<uint32_t> depth(S.n_slots, 0), sbase(S.n_slots, 0);
     for (uint32_t s : A.order) {
         const int32_t p = A.slot_parent[s];
-        world[s] = aff_mul(p < 0 ? aff_identity() : world[p], S.fwd[s]);
-    }
-    for (uint32_t s : A.order) {
+        world[s] = aff_mul(p < 0 ? aff_identity() : world[p], fwd[s]);
         Aff inv;
         if (!aff_inverse(world[s], inv)) return fail(SVO_EINVAL, "transform of slot %u is singular", s);
         const float* cell = &S.slot_cell[4 * s];
         const uint32_t K = A.slot_height[s];
         const double g = std::ldexp(1.0, (int)K) / (double)cell[3];
-        svo::FrameRec& F = out[n_frames++];
-        std::memset(&F, 0, sizeof F);
+        svo::FrameRec& F = rec[1 + s];
         for (int r = 0; r < 3; ++r) {
             for (int c = 0; c < 3; ++c) F.m[4 * r + c] = (float)(g * inv.m[r][c]);
             F.m[4 * r + 3] = (float)(g * (inv.m[r][3] - (double)cell[r]));
@@ -394,8 +419,7 @@ int build_frames(Scene& S, svo::FrameRec* out, uint32_t& n_frames, uint32_t& n_c
         F.info = A.slot_mask[s] | (K << svo::FR_K_SHIFT);
         F.inst = s;
         F.root = A.slot_node[s];
-        // containment of the moved cell in its static cell (parent frame)
-        const int32_t p = A.slot_parent[s];
+        // does the moved cell stay inside its static cell (parent frame)?
         double pmin[3], psize;
         if (p < 0) {
             for (int a = 0; a < 3; ++a) pmin[a] = S.root_min[a];
@@ -405,24 +429,33 @@ int build_frames(Scene& S, svo::FrameRec* out, uint32_t& n_frames, uint32_t& n_c
             psize = S.slot_cell[4 * p + 3];
         }
         const double csize = psize / std::ldexp(1.0, (int)A.slot_level[s]);
+        const double margin = 1e-5 * csize;
         bool inside = true;
         for (int k = 0; k < 8 && inside; ++k) {
             double x[3];
             for (int a = 0; a < 3; ++a) x[a] = cell[a] + (((k >> a) & 1) ? cell[3] : 0.0);
             for (int r = 0; r < 3; ++r) {
-                const double v = S.fwd[s].m[r][0] * x[0] + S.fwd[s].m[r][1] * x[1] + S.fwd[s].m[r][2] * x[2] +
-                                 S.fwd[s].m[r][3];
+                const double v = fwd[s].m[r][0] * x[0] + fwd[s].m[r][1] * x[1] + fwd[s].m[r][2] * x[2] +
+                                 fwd[s].m[r][3];
                 const double lo = pmin[r] + A.slot_coord[s][r] * csize;
-                const double margin = 1e-5 * csize;
-                if (v < lo + margin || v > lo + csize - margin) inside = false;
+                if (!(v >= lo + margin && v <= lo + csize - margin)) inside = false;
             }
         }
-        if (inside) F.info |= svo::FR_CONTAINED;
+        const bool parent_inline = p >= 0 && (rec[1 + p].info & svo::FR_INLINE);
+        const uint32_t d = parent_inline ? depth[p] + 1 : 1;
+        if (inside && d <= svo::kMaxInlineNest) {
+            F.info |= svo::FR_INLINE;
+            depth[s] = d;
+            sbase[s] = (parent_inline ? sbase[p] : 0) + A.slot_level[s];
+            T.nest_levels = std::max(T.nest_levels, d);
+            T.stack_levels = std::max(T.stack_levels, sbase[s] + K + 1);
+            ++T.n_inline;
+        } else {
+            cand[T.n_cand++] = 1 + s;
+            T.stack_levels = std::max(T.stack_levels, K + 1);
+        }
     }
-    n_cand = n_frames - 1;
-    if (n_cand > SVO_MAX_OVERFLOW)
-        return fail(SVO_ERANGE, "%u transformed subtrees exceed the %u candidate frames a ray can merge", n_cand,
-                    SVO_MAX_OVERFLOW);
+    if (T.stack_levels > 127) return fail(SVO_ERANGE, "nested frames need %u stack levels (limit 127)", T.stack_levels);
     return SVO_OK;
 }
 
@@ -430,15 +463,16 @@ int upload_frames(Scene& S, hipStream_t stream) {
     const int k = S.cur ^ 1;
     // the staging buffer may still feed an earlier copy
     HIP_TRY(hipEventSynchronize(S.ev[k]));
-    uint32_t nf = 0, nc = 0;
-    int rc = build_frames(S, S.h_stage[k], nf, nc);
+    TableInfo T;
+    int rc = build_frames(S, S.fwd, S.h_stage[k], T);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(S.d_frames[k], S.h_stage[k], (size_t)nf * sizeof(svo::FrameRec), hipMemcpyHostToDevice,
-                           stream));
+    HIP_TRY(hipMemcpyAsync(S.d_table[k], S.h_stage[k], S.table_bytes, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(S.ev[k], stream));
     S.cur = k;
-    S.n_frames = nf;
-    S.n_cand = nc;
+    S.n_cand = T.n_cand;
+    S.stack_levels = T.stack_levels;
+    S.nest_levels = T.nest_levels;
+    S.n_inline = T.n_inline;
     return SVO_OK;
 }
 
@@ -503,6 +537,11 @@ void svo_destroy(svo_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (auto& kv : ctx->scenes) free_scene(*kv.second);
     ctx->scenes.clear();
+    for (auto& b : ctx->batch) {
+        if (b.dev) (void)hipFree(b.dev);
+        if (b.host) (void)hipHostFree(b.host);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+    }
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
     delete ctx;
 }
@@ -540,17 +579,17 @@ int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t r
             S->world_child = (uint32_t)st;
             S->world_mask = nd_mask(nodes[root]);
         }
-        S->stack_levels = std::max<uint32_t>(S->an.max_height, 1) + 1;
         HIP_TRY(hipSetDevice(ctx->device));
         const size_t nb = std::max<uint64_t>(n_nodes, 1) * sizeof(uint64_t);
         if (hipMalloc((void**)&S->d_nodes, nb) != hipSuccess) {
             free_scene(*S);
             return fail(SVO_ENOMEM, "device allocation of %zu bytes failed", nb);
         }
-        const uint32_t max_frames = S->an.n_frames;
-        const size_t fb = (size_t)max_frames * sizeof(svo::FrameRec);
+        S->n_frames = 1 + n_slots;
+        S->table_bytes = (size_t)S->n_frames * sizeof(svo::FrameRec) + (size_t)n_slots * sizeof(uint32_t) + 16;
+        const size_t fb = S->table_bytes;
         for (int k = 0; k < 2; ++k) {
-            if (hipMalloc((void**)&S->d_frames[k], fb) != hipSuccess ||
+            if (hipMalloc((void**)&S->d_table[k], fb) != hipSuccess ||
                 hipHostMalloc((void**)&S->h_stage[k], fb, hipHostMallocDefault) != hipSuccess ||
                 hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming) != hipSuccess) {
                 free_scene(*S);
@@ -597,6 +636,21 @@ int svo_scene_bytes(svo_ctx* ctx, svo_scene scene, uint64_t* bytes) {
     Scene* S = find_scene(ctx, scene);
     if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
     *bytes = S->bytes;
+    return SVO_OK;
+}
+
+int svo_get_scene_stats(svo_ctx* ctx, svo_scene scene, svo_scene_stats* out) {
+    if (!ctx || !out) return fail(SVO_EINVAL, "ctx and out must not be NULL");
+    Scene* S = find_scene(ctx, scene);
+    if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    std::memset(out, 0, sizeof *out);
+    out->device_bytes = S->bytes;
+    out->n_slots = S->n_slots;
+    out->n_frames = S->an.n_frames;
+    out->n_inline = S->n_inline;
+    out->n_candidates = S->n_cand;
+    out->stack_levels = S->stack_levels;
+    out->nest_levels = S->nest_levels;
     return SVO_OK;
 }
 
@@ -647,8 +701,55 @@ int svo_set_config(svo_ctx* ctx, const svo_config* cfg) {
     const int rc = check_config(c);
     if (rc) return rc;
     ctx->cfg = c;
+    for (auto& kv : ctx->scenes) kv.second->tuned = false;
     return SVO_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+int queue_slot(svo_ctx* ctx, hipStream_t st, uint32_t& qslot) {
+    auto it = ctx->stream_slot.find(st);
+    if (it == ctx->stream_slot.end()) {
+        if (ctx->stream_slot.size() >= kMaxStreams) return fail(SVO_ERANGE, "more than %u streams", kMaxStreams);
+        qslot = (uint32_t)ctx->stream_slot.size();
+        ctx->stream_slot[st] = qslot;
+    } else {
+        qslot = it->second;
+    }
+    return SVO_OK;
+}
+
+// Size LDS (shrinking the node cache if needed) and launch.
+int launch(svo_ctx* ctx, const svo_config& c, svo::TraceArgs& a, hipStream_t st) {
+    size_t lds = svo::trace_lds_bytes(a, c.waves_per_block);
+    while (lds > ctx->max_lds && a.lds_nodes > 0) {
+        a.lds_nodes = (a.lds_nodes / 2) & ~1u;
+        lds = svo::trace_lds_bytes(a, c.waves_per_block);
+    }
+    if (lds > ctx->max_lds) return fail(SVO_ERANGE, "launch needs %zu bytes of LDS per work-group", lds);
+    if (!a.jobs && a.job0.lds_nodes) a.job0.lds_nodes = a.lds_nodes;
+    svo::LaunchCfg L{};
+    L.waves_per_block = c.waves_per_block;
+    const uint64_t tiles = (a.n_rays + 63) / 64;
+    const uint64_t want = (tiles + c.waves_per_block - 1) / c.waves_per_block;
+    const uint64_t cap = (uint64_t)ctx->n_cu * c.blocks_per_cu;
+    L.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+    L.lds_bytes = lds;
+    const hipError_t e = svo::launch_trace(a, L, st);
+    if (e != hipSuccess) return fail(SVO_EDEVICE, "trace launch failed: %s", hipGetErrorString(e));
+    return SVO_OK;
+}
+
+void fill_common(const svo_config& c, svo::TraceArgs& a) {
+    a.refill = (c.refill_lanes == 0 || c.refill_lanes > 64) ? 64u : c.refill_lanes;
+    a.step_limit = c.step_limit;
+}
+
+}  // namespace
+
+extern "C" {
 
 int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                    uint32_t* out_inst, float* out_t, float* out_normal, void* stream) {
@@ -658,50 +759,282 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     if (n == 0) return SVO_OK;
     if (!rays || !out_id || !out_t) return fail(SVO_EINVAL, "rays, out_id and out_t are required");
     if (((uintptr_t)rays) & 15u) return fail(SVO_EINVAL, "rays must be 16-byte aligned");
-    if (n > (uint64_t)0xFFFFFFFFu * 64u) return fail(SVO_ERANGE, "too many rays in one call");
+    if (n > 0xFF000000ull) return fail(SVO_ERANGE, "at most 0xff000000 rays per call");
     hipStream_t st = (hipStream_t)stream;
     uint32_t qslot;
-    auto it = ctx->stream_slot.find(st);
-    if (it == ctx->stream_slot.end()) {
-        if (ctx->stream_slot.size() >= kMaxStreams) return fail(SVO_ERANGE, "more than %u streams", kMaxStreams);
-        qslot = (uint32_t)ctx->stream_slot.size();
-        ctx->stream_slot[st] = qslot;
-    } else {
-        qslot = it->second;
-    }
+    int rc = queue_slot(ctx, st, qslot);
+    if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    const svo_config& c = ctx->cfg;
     svo::TraceArgs a{};
-    a.nodes = S->d_nodes;
-    a.frames = S->d_frames[S->cur];
+    const svo_config& cfg = S->tuned ? S->cfg : ctx->cfg;
+    const uint32_t cache = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, S->n_nodes) & ~1u;
+    a.jobs = nullptr;
+    a.job0 = svo::JobRec{S->d_nodes, reinterpret_cast<const float4*>(rays), out_id, out_inst, out_t, out_normal,
+                         0, 0, 0, S->n_cand, cache};
+    a.frames = reinterpret_cast<const svo::FrameRec*>(S->d_table[S->cur]);
+    a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + (size_t)S->n_frames * sizeof(svo::FrameRec));
+    a.n_jobs = 1;
     a.n_frames = S->n_frames;
-    a.n_cand = S->n_cand;
-    a.rays = reinterpret_cast<const float4*>(rays);
+    a.n_cand_total = S->n_cand;
+    a.max_cand = S->n_cand;
     a.n_rays = n;
-    a.out_id = out_id;
-    a.out_inst = out_inst;
-    a.out_t = out_t;
-    a.out_n = out_normal;
+    a.cache_src = S->d_nodes;
     a.queue = ctx->d_queue + 2 * qslot;
-    a.stack_levels = S->stack_levels;
-    a.step_limit = c.step_limit;
-    uint32_t cache = (uint32_t)std::min<uint64_t>(c.lds_cache_nodes, S->n_nodes);
-    size_t lds = svo::trace_lds_bytes(cache, a.n_frames, a.stack_levels, c.waves_per_block);
-    while (lds > ctx->max_lds && cache > 0) {
-        cache /= 2;
-        lds = svo::trace_lds_bytes(cache, a.n_frames, a.stack_levels, c.waves_per_block);
-    }
-    if (lds > ctx->max_lds) return fail(SVO_ERANGE, "scene needs %zu bytes of LDS per work-group", lds);
     a.lds_nodes = cache;
-    svo::LaunchCfg L{};
-    L.waves_per_block = c.waves_per_block;
-    const uint64_t tiles = (n + 63) / 64;
-    const uint64_t want = (tiles + c.waves_per_block - 1) / c.waves_per_block;
-    const uint64_t cap = (uint64_t)ctx->n_cu * c.blocks_per_cu;
-    L.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
-    L.lds_bytes = lds;
-    const hipError_t e = svo::launch_trace(a, L, st);
-    if (e != hipSuccess) return fail(SVO_EDEVICE, "trace launch failed: %s", hipGetErrorString(e));
+    a.stack_levels = S->stack_levels;
+    a.nest_levels = S->nest_levels;
+    a.sort_cand = S->n_cand <= svo::kMaxSortedCand ? 1u : 0u;
+    fill_common(cfg, a);
+    return launch(ctx, cfg, a, st);
+}
+
+int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    if (n_jobs && !jobs) return fail(SVO_EINVAL, "jobs is NULL");
+    try {
+        // validate and size
+        struct Plan {
+            Scene* S;
+            const svo_job* j;
+            uint32_t frame_base, cand_base;
+            std::vector<unsigned char> table;   // job-specific transforms (else the scene's current table)
+            TableInfo T;
+        };
+        std::vector<Plan> plan;
+        uint64_t total = 0;
+        uint32_t frames = 0, cands = 0;
+        std::map<const uint64_t*, uint64_t> rays_per_pool;
+        for (uint32_t i = 0; i < n_jobs; ++i) {
+            const svo_job& J = jobs[i];
+            Scene* S = find_scene(ctx, J.scene);
+            if (!S) return fail(SVO_EINVAL, "job %u: unknown scene %u", i, J.scene);
+            if (J.n == 0) continue;
+            if (!J.rays || !J.out_id || !J.out_t) return fail(SVO_EINVAL, "job %u: rays, out_id and out_t are required", i);
+            if (((uintptr_t)J.rays) & 15u) return fail(SVO_EINVAL, "job %u: rays must be 16-byte aligned", i);
+            Plan P{S, &J, frames, cands, {}, TableInfo()};
+            if (J.fwd_3x4) {
+                std::vector<Aff> fwd(S->n_slots);
+                for (uint32_t s = 0; s < S->n_slots; ++s) {
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 4; ++c) {
+                            const float v = J.fwd_3x4[12 * s + 4 * r + c];
+                            if (!std::isfinite(v)) return fail(SVO_EINVAL, "job %u: transform of slot %u is not finite", i, s);
+                            fwd[s].m[r][c] = v;
+                        }
+                }
+                P.table.resize(S->table_bytes);
+                const int rc = build_frames(*S, fwd, P.table.data(), P.T);
+                if (rc) return rc;
+            } else {
+                P.T.n_cand = S->n_cand;
+                P.T.stack_levels = S->stack_levels;
+                P.T.nest_levels = S->nest_levels;
+            }
+            frames += S->n_frames;
+            cands += P.T.n_cand;
+            total += J.n;
+            rays_per_pool[S->d_nodes] += J.n;
+            plan.push_back(std::move(P));
+        }
+        if (plan.empty()) return SVO_OK;
+        if (plan.size() > svo::kMaxJobs) return fail(SVO_ERANGE, "at most %u non-empty jobs per batch", svo::kMaxJobs);
+        if (frames > 2047) return fail(SVO_ERANGE, "a batch may hold at most 2047 frame records (has %u)", frames);
+        if (total > 0xFF000000ull) return fail(SVO_ERANGE, "at most 0xff000000 rays per batch");
+        hipStream_t st = (hipStream_t)stream;
+        uint32_t qslot;
+        int rc = queue_slot(ctx, st, qslot);
+        if (rc) return rc;
+        HIP_TRY(hipSetDevice(ctx->device));
+
+        // node cache: the pool with the most rays in this batch
+        const uint64_t* cache_src = nullptr;
+        uint64_t best = 0;
+        for (auto& kv : rays_per_pool)
+            if (kv.second > best) { best = kv.second; cache_src = kv.first; }
+        uint64_t cache_pool_nodes = 0;
+        const svo_config* pcfg = &ctx->cfg;
+        for (auto& P : plan)
+            if (P.S->d_nodes == cache_src) {
+                cache_pool_nodes = P.S->n_nodes;
+                if (P.S->tuned) pcfg = &P.S->cfg;
+            }
+        const svo_config& cfg = *pcfg;
+        const uint32_t cache = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, cache_pool_nodes) & ~1u;
+
+        // pack [jobs][frames][candidates]
+        const size_t jb = plan.size() * sizeof(svo::JobRec);
+        const size_t fb = (size_t)frames * sizeof(svo::FrameRec);
+        const size_t bytes = jb + fb + (size_t)cands * sizeof(uint32_t) + 16;
+        auto& B = ctx->batch[ctx->next_batch];
+        ctx->next_batch = (ctx->next_batch + 1) % 4;
+        if (B.ev) HIP_TRY(hipEventSynchronize(B.ev));
+        if (B.cap < bytes) {
+            if (B.dev) (void)hipFree(B.dev);
+            if (B.host) (void)hipHostFree(B.host);
+            B.dev = nullptr;
+            B.host = nullptr;
+            B.cap = 0;
+            const size_t cap = std::max<size_t>(bytes, 64 << 10);
+            if (hipMalloc((void**)&B.dev, cap) != hipSuccess || hipHostMalloc((void**)&B.host, cap, hipHostMallocDefault) != hipSuccess)
+                return fail(SVO_ENOMEM, "batch table allocation failed");
+            B.cap = cap;
+        }
+        if (!B.ev) HIP_TRY(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+        svo::JobRec* jr = reinterpret_cast<svo::JobRec*>(B.host);
+        svo::FrameRec* fr = reinterpret_cast<svo::FrameRec*>(B.host + jb);
+        uint32_t* cr = reinterpret_cast<uint32_t*>(B.host + jb + fb);
+        uint64_t begin = 0;
+        svo::TraceArgs a{};
+        uint32_t max_cand = 0;
+        for (size_t i = 0; i < plan.size(); ++i) {
+            Plan& P = plan[i];
+            Scene& S = *P.S;
+            const unsigned char* tab = P.table.empty() ? S.h_stage[S.cur] : P.table.data();
+            std::memcpy(fr + P.frame_base, tab, (size_t)S.n_frames * sizeof(svo::FrameRec));
+            const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + (size_t)S.n_frames * sizeof(svo::FrameRec));
+            for (uint32_t c = 0; c < P.T.n_cand; ++c) cr[P.cand_base + c] = P.frame_base + sc[c];
+            const svo_job& J = *P.j;
+            jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
+                                J.out_normal, begin, P.frame_base, P.cand_base, P.T.n_cand,
+                                S.d_nodes == cache_src ? cache : 0u};
+            begin += J.n;
+            max_cand = std::max(max_cand, P.T.n_cand);
+            a.stack_levels = std::max(a.stack_levels, P.T.stack_levels);
+            a.nest_levels = std::max(a.nest_levels, P.T.nest_levels);
+        }
+        a.jobs = reinterpret_cast<const svo::JobRec*>(B.dev);
+        a.frames = reinterpret_cast<const svo::FrameRec*>(B.dev + jb);
+        a.cand = reinterpret_cast<const uint32_t*>(B.dev + jb + fb);
+        a.n_jobs = (uint32_t)plan.size();
+        a.n_frames = frames;
+        a.n_cand_total = cands;
+        a.max_cand = max_cand;
+        a.n_rays = total;
+        a.cache_src = cache_src;
+        a.queue = ctx->d_queue + 2 * qslot;
+        a.lds_nodes = cache;
+        a.sort_cand = max_cand <= svo::kMaxSortedCand ? 1u : 0u;
+        fill_common(cfg, a);
+        // size LDS now: a smaller node cache changes the jobs' lds_nodes
+        size_t lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
+        while (lds > ctx->max_lds && a.lds_nodes > 0) {
+            a.lds_nodes = (a.lds_nodes / 2) & ~1u;
+            lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
+        }
+        for (size_t i = 0; i < plan.size(); ++i)
+            if (jr[i].lds_nodes) jr[i].lds_nodes = a.lds_nodes;
+        HIP_TRY(hipMemcpyAsync(B.dev, B.host, bytes, hipMemcpyHostToDevice, st));
+        rc = launch(ctx, cfg, a, st);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(B.ev, st));
+        return SVO_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SVO_ENOMEM, "out of host memory");
+    }
+}
+
+int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n, void* stream, svo_config* best) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    Scene* S = find_scene(ctx, scene);
+    if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    if (n == 0 || !sample_rays) return fail(SVO_EINVAL, "svo_tune needs sample rays");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    uint32_t* d_id = nullptr;
+    float* d_t = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (d_id) (void)hipFree(d_id);
+        if (d_t) (void)hipFree(d_t);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc((void**)&d_id, n * sizeof(uint32_t)) != hipSuccess || hipMalloc((void**)&d_t, n * sizeof(float)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(SVO_ENOMEM, "tuner scratch allocation failed");
+    }
+    const svo_config base = ctx->cfg;
+    const bool was_tuned = S->tuned;
+    const svo_config was_cfg = S->cfg;
+    svo_config win = base;
+    float win_ms = 1e30f;
+    static const uint32_t kWaves[] = {2, 4, 8};
+    static const uint32_t kBlocks[] = {1, 2, 3, 4, 6, 8};
+    static const uint32_t kCache[] = {0, 1024, 4096};
+    static const uint32_t kRefill[] = {0, 48};
+    int rc = SVO_OK;
+    for (uint32_t w : kWaves)
+        for (uint32_t b : kBlocks) {
+            if (w * b > 32) continue;  // resident waves per CU
+            for (uint32_t c : kCache)
+                for (uint32_t r : kRefill) {
+                    svo_config cand = base;
+                    cand.waves_per_block = w;
+                    cand.blocks_per_cu = b;
+                    cand.lds_cache_nodes = c;
+                    cand.refill_lanes = r;
+                    S->tuned = true;
+                    S->cfg = cand;
+                    rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
+                    if (rc == SVO_ERANGE) continue;  // does not fit in LDS
+                    if (rc) break;
+                    HIP_TRY(hipEventRecord(e0, st));
+                    for (int k = 0; k < 3 && rc == SVO_OK; ++k)
+                        rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
+                    if (rc) break;
+                    HIP_TRY(hipEventRecord(e1, st));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < win_ms) {
+                        win_ms = ms;
+                        win = cand;
+                    }
+                }
+            if (rc && rc != SVO_ERANGE) break;
+        }
+    cleanup();
+    if (rc && rc != SVO_ERANGE) {
+        S->tuned = was_tuned;
+        S->cfg = was_cfg;
+        return rc;
+    }
+    if (win_ms >= 1e30f) {
+        S->tuned = was_tuned;
+        S->cfg = was_cfg;
+        return fail(SVO_ERANGE, "no candidate configuration fits this scene");
+    }
+    S->tuned = true;
+    S->cfg = win;
+    if (best) *best = win;
+    return SVO_OK;
+}
+
+int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream) {
+    if (!ctx || !cam || !out_rays) return fail(SVO_EINVAL, "ctx, cam and out_rays are required");
+    if (((uintptr_t)out_rays) & 15u) return fail(SVO_EINVAL, "out_rays must be 16-byte aligned");
+    if (cam->width == 0 || cam->height == 0 || cam->samples == 0) return fail(SVO_EINVAL, "empty image");
+    if ((uint64_t)cam->width * cam->height * cam->samples > 0xFF000000ull) return fail(SVO_ERANGE, "too many rays");
+    if (!(cam->tan_half_fov > 0.f) || !std::isfinite(cam->tan_half_fov)) return fail(SVO_EINVAL, "bad field of view");
+    svo::CameraArgs c{};
+    for (int a = 0; a < 3; ++a) {
+        c.eye[a] = cam->eye[a];
+        c.fwd[a] = cam->forward[a];
+        c.right[a] = cam->right[a];
+        c.up[a] = cam->up[a];
+    }
+    c.tan_half_fov = cam->tan_half_fov;
+    c.aspect = (float)cam->width / (float)cam->height;
+    c.width = cam->width;
+    c.height = cam->height;
+    c.samples = cam->samples;
+    c.seed = cam->seed;
+    c.jitter = cam->jitter ? 1u : 0u;
+    c.tiled = cam->tiled ? 1u : 0u;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const hipError_t e = svo::launch_primary_rays(c, out_rays, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SVO_EDEVICE, "ray generation launch failed: %s", hipGetErrorString(e));
     return SVO_OK;
 }
 

@@ -2,14 +2,16 @@
 #pragma once
 
 #include <hip/hip_runtime_api.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace svo {
 
-// One frame of a scene, as the device reads it: 64 bytes, cached in LDS.
-// The map takes a world point to the frame's grid coordinates, where the frame's root cell is [0, 2^K)^3 and a leaf at depth
-// l spans 2^(K-l) units: g = M x + c (paper Eq. 3 with the scale of
-// Sec. 3.2 and the grid scaling folded into one affine map).
+// One frame of a scene as the device reads it: 64 bytes, held in LDS.  The
+// map takes a world point to the frame's grid coordinates, where the frame's
+// root cell is [0, 2^K)^3 and a leaf at depth l spans 2^(K-l) units:
+// g = M x + c (paper Eq. 3, with the scale of Sec. 3.2 and the grid scaling
+// folded into one affine map).  Record 0 is the world, record 1 + s slot s.
 struct alignas(16) FrameRec {
     float m[12];        // rows r = 0..2: m[4r..4r+2] = row r of M, m[4r+3] = c_r
     uint32_t child;     // child group start of the frame root
@@ -24,24 +26,51 @@ enum : uint32_t {
     FR_K_SHIFT = 8,           // bits 8..12: height K (levels below the frame root)
     FR_K_MASK = 0x1Fu,
     FR_ROOT_LEAF = 1u << 13,  // the frame root itself is a solid leaf (world only)
-    FR_EMPTY = 1u << 14,      // nothing to trace in this frame
-    FR_CONTAINED = 1u << 15,  // moved content stays inside the static cell
+    FR_EMPTY = 1u << 14,      // nothing to trace in this frame (unused slot, empty world)
+    FR_INLINE = 1u << 15,     // moved content stays in its static cell: entered in place
 };
 
-struct TraceArgs {
-    const uint64_t* nodes;
-    const FrameRec* frames;   // [0] = world, [1 .. n_cand] = candidate frames
-    uint32_t n_frames;        // records copied to LDS
-    uint32_t n_cand;          // candidate (overflowing) frames, <= 64
+// Frames entered in place may nest this deep inside one top-level frame.
+constexpr uint32_t kMaxInlineNest = 4;
+// Per-lane candidate entry tables are kept in LDS up to this many candidates.
+constexpr uint32_t kMaxSortedCand = 16;
+
+// One job of a launch: a ray range traced against one scene under one set
+// of transforms (80 bytes, held in LDS).
+struct alignas(16) JobRec {
+    const uint64_t* nodes;    // the scene's pool
     const float4* rays;       // 2 x float4 per ray
-    uint64_t n_rays;
     uint32_t* out_id;
     uint32_t* out_inst;       // nullable
     float* out_t;
     float* out_n;             // nullable, 3 floats per ray
-    uint32_t* queue;          // [0] next tile, [1] finished work-groups
-    uint32_t lds_nodes;       // pool prefix cached in LDS
-    uint32_t stack_levels;    // stack entries per lane (>= max frame height)
+    uint64_t ray_begin;       // first launch-wide ray index of this job
+    uint32_t frame_base;      // the job's world record in the launch's frame array
+    uint32_t cand_base;       // the job's first entry in the launch's candidate list
+    uint32_t n_cand;
+    uint32_t lds_nodes;       // pool prefix of this job's scene held in LDS (0: none)
+};
+static_assert(sizeof(JobRec) == 80, "job record must be 80 bytes");
+
+constexpr uint32_t kMaxJobs = 256;
+
+struct TraceArgs {
+    const JobRec* jobs;       // device job table, or nullptr: the single job in job0
+    JobRec job0;
+    const FrameRec* frames;   // n_frames records; job j's slot s is frames[frame_base_j + 1 + s]
+    const uint32_t* cand;     // candidate frames (absolute indices), per job contiguous
+    uint32_t n_jobs;
+    uint32_t n_frames;
+    uint32_t n_cand_total;
+    uint32_t max_cand;        // largest per-job candidate count
+    uint64_t n_rays;          // all jobs
+    const uint64_t* cache_src;  // pool whose prefix is cached in LDS
+    uint32_t* queue;          // [0] rays claimed, [1] finished work-groups
+    uint32_t lds_nodes;       // pool prefix cached in LDS (even)
+    uint32_t stack_levels;    // traversal stack entries per lane
+    uint32_t nest_levels;     // frame stack entries per lane (inline frames)
+    uint32_t sort_cand;       // 1: candidates in entry order via a per-lane LDS table
+    uint32_t refill;          // a wave claims new rays once this many lanes are idle (1..64)
     uint32_t step_limit;
 };
 
@@ -51,7 +80,18 @@ struct LaunchCfg {
     size_t lds_bytes;
 };
 
-size_t trace_lds_bytes(uint32_t lds_nodes, uint32_t n_frames, uint32_t stack_levels, uint32_t waves_per_block);
+// Pinhole camera for device-side primary rays (see svo_raygen.hip).
+struct CameraArgs {
+    float eye[3], fwd[3], right[3], up[3];
+    float tan_half_fov, aspect;
+    uint32_t width, height, samples, seed;
+    uint32_t jitter;   // 0: pixel centres
+    uint32_t tiled;    // 1: 8x8 tile order
+};
+
+hipError_t launch_primary_rays(const CameraArgs& c, float* out, hipStream_t stream);
+
+size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block);
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream);
 
 }  // namespace svo

@@ -1,26 +1,29 @@
 // First-hit traversal of sparse voxel octrees with transformed subtrees, for
-// gfx950 (wave64, no matrix cores: the work is dependent 8-byte gathers).
+// gfx950 (wave64; no matrix cores: the work is dependent 8-byte gathers).
 //
 // Per ray (one lane each):
 //   1. map the world ray into a frame's grid coordinates (paper Eq. 2-3 with
 //      the scale folded into the affine map, Sec. 3.2); t is not rescaled;
-//   2. mirror axes with negative direction so every direction component is
-//      positive; a plane crossing is then t(v) = v * invd + bias, one FMA,
-//      evaluated by the same formula for every cell sharing that plane;
-//   3. walk the frame's octree front to back, top-down (the role Revelles'
-//      parametric traversal plays in the paper, Sec. 5): integer cell
-//      corners, a per-level stack of (child start, mask) in LDS, and an exit
-//      by the highest changed coordinate bit, so popping needs no search;
-//   4. frames whose moved content leaves their static cell are candidates,
-//      tried in order of root-cell entry and skipped once their entry lies
-//      beyond the best hit (the depth sort of Sec. 4.2 with an exact slab
-//      cull in place of the bounding sphere of Sec. 4.1);
-//   5. write id, slot, t and the normal (entry face mapped by the inverse
-//      transpose).
+//   2. mirror axes with a negative direction so every component is positive;
+//      a plane crossing is then t(v) = v * invd + bias, one FMA, evaluated by
+//      the same formula for every cell sharing that plane;
+//   3. walk the frame's octree front to back, top-down (the role of the
+//      parametric traversal in the paper, Sec. 5): integer cell corners, a
+//      per-level LDS stack of (child start, mask), and an exit by the highest
+//      changed coordinate bit, so popping needs no search;
+//   4. at a transformed node whose moved content stays inside its static
+//      cell, switch into that node's frame in place (Sec. 3, Fig. 1: the ray,
+//      not the model, is transformed) and resume the enclosing walk after it;
+//   5. transformed subtrees that leave their static cell are candidates,
+//      traced from their own roots in order of root-cell entry and skipped
+//      once the entry lies beyond the best hit (the depth sort of Sec. 4.2,
+//      with an exact slab test in place of the bounding sphere of Sec. 4.1);
+//   6. write id, slot, t and the normal (entry face, inverse transpose).
 //
-// Work distribution: a persistent grid; each wave claims 64-ray tiles from
-// a global counter, and the last work-group to finish resets the counter so
-// the next launch on the stream starts from zero.
+// Work distribution: a persistent grid.  Each wave keeps 64 rays in flight
+// and claims new ones from a global counter once `refill` lanes are idle (64
+// = whole tiles).  The last work-group to finish resets the counter so the
+// next launch on the stream starts from zero.
 #include <hip/hip_runtime.h>
 
 #include "svo_internal.h"
@@ -31,6 +34,10 @@ namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kStepLimitId = 0xFFFFFFFEu;
+constexpr uint32_t kXform = 0x80000000u;
+
+enum : uint32_t { M_DONE = 0, M_WALK = 1, M_SELECT = 2 };
+enum : uint32_t { EV_NONE = 0, EV_HIT = 1, EV_ENTER = 2, EV_END = 3, EV_LIMIT = 4 };
 
 struct Ray {
     float ox, oy, oz, tmin, dx, dy, dz, tmax;
@@ -41,14 +48,14 @@ struct FrameRay {
     float ix, iy, iz;   // 1 / |d_a|
     float bx, by, bz;   // t(v) = v * i_a + b_a for the mirrored plane v
     uint32_t flip;      // bit a: d_a < 0 in the frame (axis mirrored)
-    uint32_t K;
+    uint32_t K;         // frame height
 };
 
 __device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
-// Map the ray into frame F and clip it to the root cell [0, 2^K)^3.
-// Returns false when the clipped interval [t0, t1] is empty.  eaxis = axis
+// Map the ray into frame F and clip it to the root cell [0, 2^K)^3 and
+// [tmin, tlimit].  Returns false when that interval is empty.  eaxis = axis
 // of the entry face, 3 when the ray starts inside (t0 = tmin).
 __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, float tlimit, FrameRay& fr, float& t0,
                                             int& eaxis) {
@@ -86,85 +93,6 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
     return te <= fminf(tx, tlimit);
 }
 
-// Front-to-back walk of one frame.  Returns 1 on a hit (t_hit, id_hit,
-// axis_hit set), 0 when the frame has no hit before tlimit, 2 when the step
-// limit is reached.  stk points at this lane's column of the wave's stack
-// (entry for level l at stk[l * 64]).
-__device__ __forceinline__ int frame_walk(const uint64_t* __restrict__ nodes, const uint64_t* lds_nodes,
-                                          uint32_t n_lds, uint2* stk, const FrameRec& F, const FrameRay& fr,
-                                          float t0, int eaxis, float tlimit, uint32_t step_limit, uint32_t& steps,
-                                          float& t_hit, uint32_t& id_hit, int& axis_hit) {
-    const uint32_t K = fr.K;
-    uint32_t pmask = F.info & FR_MASK;
-    uint32_t pchild = F.child;
-    uint32_t lvl = 1;
-    uint32_t size = 1u << (K - 1);
-    // first child: upper half on every axis whose mid plane is crossed before entry
-    uint32_t px = (fmaf((float)size, fr.ix, fr.bx) <= t0) ? size : 0u;
-    uint32_t py = (fmaf((float)size, fr.iy, fr.by) <= t0) ? size : 0u;
-    uint32_t pz = (fmaf((float)size, fr.iz, fr.bz) <= t0) ? size : 0u;
-    float tc0 = t0;
-    for (;;) {
-        if (++steps > step_limit) return 2;
-        const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
-        const float ey = fmaf((float)(py + size), fr.iy, fr.by);
-        const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
-        const float tc1 = min3f(ex, ey, ez);
-        const uint32_t oct = (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
-        if ((pmask >> oct) & 1u) {
-            const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
-            const uint64_t w = (cidx < n_lds) ? lds_nodes[cidx] : nodes[cidx];
-            const uint32_t w0 = (uint32_t)w;
-            const uint32_t w1 = (uint32_t)(w >> 32);
-            const uint32_t cm = w0 & 0xFFu;
-            if (cm == 0u) {
-                t_hit = tc0;
-                id_hit = cidx;
-                axis_hit = eaxis;
-                return 1;
-            }
-            if (!(w1 & 0x80000000u)) {
-                stk[lvl * 64] = make_uint2(pchild, pmask);
-                const uint32_t c24 = w0 >> 8;
-                pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
-                pmask = cm;
-                ++lvl;
-                size >>= 1;
-                px += (fmaf((float)(px + size), fr.ix, fr.bx) <= tc0) ? size : 0u;
-                py += (fmaf((float)(py + size), fr.iy, fr.by) <= tc0) ? size : 0u;
-                pz += (fmaf((float)(pz + size), fr.iz, fr.bz) <= tc0) ? size : 0u;
-                continue;
-            }
-            // a transformed child belongs to another frame: empty here
-        }
-        // leave the current cell through its nearest exit plane(s)
-        if (tc1 > tlimit) return 0;
-        const uint32_t step = (ex == tc1 ? 1u : 0u) | (ey == tc1 ? 2u : 0u) | (ez == tc1 ? 4u : 0u);
-        if (step == 0u) return 0;  // non-finite crossing: nothing more to find
-        const uint32_t nx = px + ((step & 1u) ? size : 0u);
-        const uint32_t ny = py + ((step & 2u) ? size : 0u);
-        const uint32_t nz = pz + ((step & 4u) ? size : 0u);
-        const uint32_t diff = (nx ^ px) | (ny ^ py) | (nz ^ pz);
-        const uint32_t h = 31u - __clz(diff);
-        if (h >= K) return 0;  // left the frame's root cell
-        const uint32_t nsize = 1u << h;
-        const uint32_t keep = ~(nsize - 1u);
-        px = nx & keep;
-        py = ny & keep;
-        pz = nz & keep;
-        const uint32_t nlvl = K - h;
-        if (nlvl < lvl) {
-            const uint2 e = stk[nlvl * 64];
-            pchild = e.x;
-            pmask = e.y;
-        }
-        lvl = nlvl;
-        size = nsize;
-        tc0 = tc1;
-        eaxis = __ffs(step) - 1;
-    }
-}
-
 __device__ __forceinline__ bool ray_valid(const Ray& r) {
     const bool fin = isfinite(r.ox) && isfinite(r.oy) && isfinite(r.oz) && isfinite(r.dx) && isfinite(r.dy) &&
                      isfinite(r.dz);
@@ -172,129 +100,135 @@ __device__ __forceinline__ bool ray_valid(const Ray& r) {
     return fin && nonzero && !isnan(r.tmin) && !isnan(r.tmax) && r.tmin <= r.tmax && r.tmin < INFINITY;
 }
 
+__host__ __device__ __forceinline__ size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Pointers read out of LDS job records lose their address space; these
+// accessors restore it so the compiler emits global (not generic) loads and
+// stores.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, uint64_t i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, uint64_t i, T v) {
+    ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
+
 }  // namespace
+
+size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
+    const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 64 +
+                          align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec);
+    const size_t per_wave = (a.sort_cand ? (size_t)a.max_cand * 64 * 4 : 0) + (size_t)a.stack_levels * 64 * 8 +
+                            (size_t)a.nest_levels * 64 * 16;
+    return shared + per_wave * waves_per_block;
+}
 
 __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t* lds_nodes = reinterpret_cast<uint64_t*>(smem);
-    FrameRec* lds_frames = reinterpret_cast<FrameRec*>(smem + (size_t)a.lds_nodes * 8);
-    uint2* lds_stack = reinterpret_cast<uint2*>(smem + (size_t)a.lds_nodes * 8 + (size_t)a.n_frames * 64);
+    unsigned char* p = smem;
+    uint64_t* lds_nodes = reinterpret_cast<uint64_t*>(p);
+    p += align16((size_t)a.lds_nodes * 8);
+    FrameRec* lds_frames = reinterpret_cast<FrameRec*>(p);
+    p += (size_t)a.n_frames * 64;
+    uint32_t* lds_cand = reinterpret_cast<uint32_t*>(p);
+    p += align16((size_t)a.n_cand_total * 4);
+    JobRec* lds_jobs = reinterpret_cast<JobRec*>(p);
+    p += (size_t)a.n_jobs * sizeof(JobRec);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const size_t ent_bytes = a.sort_cand ? (size_t)a.max_cand * 64 * 4 : 0;
+    const size_t per_wave = ent_bytes + (size_t)a.stack_levels * 64 * 8 + (size_t)a.nest_levels * 64 * 16;
+    unsigned char* wp = p + per_wave * wave;
+    float* ent = reinterpret_cast<float*>(wp) + lane;                                   // candidate c at ent[c * 64]
+    uint2* stk = reinterpret_cast<uint2*>(wp + ent_bytes) + lane;                       // level l at stk[l * 64]
+    uint4* fst = reinterpret_cast<uint4*>(wp + ent_bytes + (size_t)a.stack_levels * 512) + lane;  // nest n at fst[n * 64]
 
-    for (uint32_t i = threadIdx.x; i < a.lds_nodes; i += blockDim.x) lds_nodes[i] = a.nodes[i];
+    for (uint32_t i = threadIdx.x; i < a.lds_nodes; i += blockDim.x) lds_nodes[i] = a.cache_src[i];
     {
         const uint4* src = reinterpret_cast<const uint4*>(a.frames);
         uint4* dst = reinterpret_cast<uint4*>(lds_frames);
         for (uint32_t i = threadIdx.x; i < a.n_frames * 4u; i += blockDim.x) dst[i] = src[i];
     }
+    for (uint32_t i = threadIdx.x; i < a.n_cand_total; i += blockDim.x) lds_cand[i] = a.cand[i];
+    if (a.jobs) {
+        const uint4* src = reinterpret_cast<const uint4*>(a.jobs);
+        uint4* dst = reinterpret_cast<uint4*>(lds_jobs);
+        for (uint32_t i = threadIdx.x; i < a.n_jobs * (uint32_t)(sizeof(JobRec) / 16); i += blockDim.x) dst[i] = src[i];
+    } else if (threadIdx.x == 0) {
+        lds_jobs[0] = a.job0;
+    }
     __syncthreads();
 
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    uint2* stk = lds_stack + (size_t)wave * a.stack_levels * 64 + lane;
+    const uint32_t refill = a.refill;
 
-    for (;;) {
-        uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&a.queue[0], 1u);
-        tile = __shfl(tile, 0);
-        const uint64_t base = (uint64_t)tile * 64u;
-        if (base >= a.n_rays) break;
-        const uint64_t i = base + lane;
-        if (i >= a.n_rays) continue;
+    // per-lane state
+    uint32_t mode = M_DONE;
+    uint64_t ri = 0;           // ray index within its job
+    uint32_t job = 0;
+    const uint64_t* nodes = nullptr;
+    uint32_t n_lds = 0, fbase = 0, cbase = 0, ncand = 0;
+    Ray r{};
+    float best_t = INFINITY, tl = 0.f;
+    uint32_t best_id = kNone, best_inst = kNone;
+    int best_f = -1, best_axis = 3;
+    uint32_t steps = 0, cnext = 0;
+    FrameRay fr{};
+    uint32_t cur_f = 0, pmask = 0, pchild = 0, px = 0, py = 0, pz = 0, size = 1, lvl = 1, sbase = 0, nest = 0;
+    float tc0 = 0.f;
+    int eaxis = 3;
+    bool resume = false;
+    bool exhausted = false;  // wave-uniform
 
-        const float4 r0 = a.rays[2 * i];
-        const float4 r1 = a.rays[2 * i + 1];
-        const Ray r{r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-
-        float best_t = INFINITY;
-        uint32_t best_id = kNone, best_inst = kNone;
-        int best_frame = -1, best_axis = 3;
-        uint32_t steps = 0;
-        bool limit = false;
-
-        if (ray_valid(r)) {
-            // world frame
-            const FrameRec& W = lds_frames[0];
-            if (!(W.info & FR_EMPTY)) {
-                FrameRay fr;
-                float t0;
-                int ea;
-                if (frame_setup(W, r, r.tmax, fr, t0, ea)) {
-                    if (W.info & FR_ROOT_LEAF) {
-                        best_t = t0;
-                        best_id = W.root;
-                        best_inst = W.inst;
-                        best_axis = ea;
-                        best_frame = 0;
-                    } else {
-                        float th;
-                        uint32_t ih;
-                        int ah;
-                        const int res = frame_walk(a.nodes, lds_nodes, a.lds_nodes, stk, W, fr, t0, ea, r.tmax,
-                                                   a.step_limit, steps, th, ih, ah);
-                        if (res == 1) {
-                            best_t = th;
-                            best_id = ih;
-                            best_inst = W.inst;
-                            best_axis = ah;
-                            best_frame = 0;
-                        } else if (res == 2) {
-                            limit = true;
-                        }
-                    }
-                }
-            }
-            // candidate frames, nearest root-cell entry first
-            uint64_t done = 0;
-            while (!limit) {
-                const float tl = fminf(r.tmax, best_t);
-                float bestc = INFINITY;
-                int pick = -1;
-                for (uint32_t c = 0; c < a.n_cand; ++c) {
-                    if ((done >> c) & 1ull) continue;
-                    FrameRay fr;
-                    float t0;
-                    int ea;
-                    if (frame_setup(lds_frames[1 + c], r, tl, fr, t0, ea) && (pick < 0 || t0 < bestc)) {
-                        bestc = t0;
-                        pick = (int)c;
-                    }
-                }
-                if (pick < 0) break;
-                done |= 1ull << pick;
-                const FrameRec& F = lds_frames[1 + pick];
-                FrameRay fr;
-                float t0;
-                int ea;
-                frame_setup(F, r, tl, fr, t0, ea);
-                float th;
-                uint32_t ih;
-                int ah;
-                const int res = frame_walk(a.nodes, lds_nodes, a.lds_nodes, stk, F, fr, t0, ea, tl, a.step_limit,
-                                           steps, th, ih, ah);
-                if (res == 1) {
-                    const uint32_t inst = F.inst;
-                    if (th < best_t || (th == best_t && (inst < best_inst || (inst == best_inst && ih < best_id)))) {
-                        best_t = th;
-                        best_id = ih;
-                        best_inst = inst;
-                        best_axis = ah;
-                        best_frame = 1 + pick;
-                    }
-                } else if (res == 2) {
-                    limit = true;
-                }
-            }
+    auto record_hit = [&](float t, uint32_t id, uint32_t f, int axis) {
+        const uint32_t inst = lds_frames[f].inst;
+        if (t < best_t || (t == best_t && (inst < best_inst || (inst == best_inst && id < best_id)))) {
+            best_t = t;
+            best_id = id;
+            best_inst = inst;
+            best_f = (int)f;
+            best_axis = axis;
+            tl = fminf(r.tmax, best_t);
         }
+    };
 
+    // Enter top-level frame f from its root.  Returns true when a walk starts.
+    auto start_frame = [&](uint32_t f) -> bool {
+        const FrameRec& F = lds_frames[f];
+        if (F.info & FR_EMPTY) return false;
+        float t0;
+        int ea;
+        if (!frame_setup(F, r, tl, fr, t0, ea)) return false;
+        if (F.info & FR_ROOT_LEAF) {
+            record_hit(t0, F.root, f, ea);
+            return false;
+        }
+        cur_f = f;
+        pmask = F.info & FR_MASK;
+        pchild = F.child;
+        lvl = 1;
+        sbase = 0;
+        nest = 0;
+        size = 1u << (fr.K - 1);
+        px = (fmaf((float)size, fr.ix, fr.bx) <= t0) ? size : 0u;
+        py = (fmaf((float)size, fr.iy, fr.by) <= t0) ? size : 0u;
+        pz = (fmaf((float)size, fr.iz, fr.bz) <= t0) ? size : 0u;
+        tc0 = t0;
+        eaxis = ea;
+        resume = false;
+        return true;
+    };
+
+    auto finish = [&]() {
         float nx = 0.f, ny = 0.f, nz = 0.f;
-        if (limit) {
-            best_id = kStepLimitId;
+        if (best_id == kStepLimitId) {
             best_inst = kNone;
             best_t = INFINITY;
-        } else if (best_frame >= 0 && best_axis < 3) {
+        } else if (best_f >= 0 && best_axis < 3) {
             // outward normal: -sgn(d_a) e_a in the frame, mapped by M^T (row a of M)
-            const FrameRec& F = lds_frames[best_frame];
-            const float* row = &F.m[4 * best_axis];
+            const float* row = &lds_frames[best_f].m[4 * best_axis];
             const float da = fmaf(row[0], r.dx, fmaf(row[1], r.dy, row[2] * r.dz));
             const float s = (da < 0.f) ? 1.f : -1.f;
             const float inv = s / sqrtf(fmaf(row[0], row[0], fmaf(row[1], row[1], row[2] * row[2])));
@@ -302,13 +236,261 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
             ny = row[1] * inv;
             nz = row[2] * inv;
         }
-        a.out_id[i] = best_id;
-        if (a.out_inst) a.out_inst[i] = best_inst;
-        a.out_t[i] = best_t;
-        if (a.out_n) {
-            a.out_n[3 * i] = nx;
-            a.out_n[3 * i + 1] = ny;
-            a.out_n[3 * i + 2] = nz;
+        const JobRec& J = lds_jobs[job];
+        gst(J.out_id, ri, best_id);
+        if (J.out_inst) gst(J.out_inst, ri, best_inst);
+        gst(J.out_t, ri, best_t);
+        if (J.out_n) {
+            gst(J.out_n, 3 * ri, nx);
+            gst(J.out_n, 3 * ri + 1, ny);
+            gst(J.out_n, 3 * ri + 2, nz);
+        }
+        mode = M_DONE;
+    };
+
+    for (;;) {
+        // ---------------------------------------------------------- refill
+        const uint64_t idle = __ballot(mode == M_DONE);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (exhausted && nidle == 64u) break;
+        if (!exhausted && nidle >= refill) {
+            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)idle) - 1u;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&a.queue[0], nidle);
+            base = __shfl(base, (int)leader);
+            if ((uint64_t)base + nidle >= a.n_rays) exhausted = true;
+            if (mode == M_DONE) {
+                const uint32_t rank =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                const uint64_t gidx = (uint64_t)base + rank;
+                if (gidx < a.n_rays) {
+                    // the job holding this launch-wide ray index (jobs are in ray order)
+                    uint32_t lo = 0, hi = a.n_jobs;
+                    while (hi - lo > 1u) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (lds_jobs[mid].ray_begin <= gidx) lo = mid; else hi = mid;
+                    }
+                    job = lo;
+                    const JobRec& J = lds_jobs[job];
+                    ri = gidx - J.ray_begin;
+                    nodes = J.nodes;
+                    n_lds = J.lds_nodes;
+                    fbase = J.frame_base;
+                    cbase = J.cand_base;
+                    ncand = J.n_cand;
+                    const v4f* rp = reinterpret_cast<const v4f*>(J.rays);
+                    const v4f r0 = gld(rp, 2 * ri);
+                    const v4f r1 = gld(rp, 2 * ri + 1);
+                    r = Ray{r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+                    best_t = INFINITY;
+                    best_id = kNone;
+                    best_inst = kNone;
+                    best_f = -1;
+                    best_axis = 3;
+                    steps = 0;
+                    cnext = 0;
+                    if (!ray_valid(r)) {
+                        finish();
+                    } else {
+                        tl = r.tmax;
+                        if (a.sort_cand) {
+                            for (uint32_t c = 0; c < ncand; ++c) {
+                                FrameRay cfr;
+                                float t0;
+                                int ea;
+                                const bool in = frame_setup(lds_frames[lds_cand[cbase + c]], r, tl, cfr, t0, ea);
+                                ent[c * 64] = in ? t0 : INFINITY;
+                            }
+                        }
+                        mode = start_frame(fbase) ? M_WALK : M_SELECT;
+                    }
+                }
+            }
+        }
+
+        // ---------------------------------------------------------- walk
+        if (mode == M_WALK) {
+            // Leave the current cell through its nearest exit plane(s); EV_END
+            // when the ray leaves the frame's root cell or passes tl.
+            auto advance = [&](float ex, float ey, float ez, float tc1) -> uint32_t {
+                const uint32_t step = (ex == tc1 ? 1u : 0u) | (ey == tc1 ? 2u : 0u) | (ez == tc1 ? 4u : 0u);
+                if (tc1 > tl || step == 0u) return EV_END;
+                const uint32_t nx = px + ((step & 1u) ? size : 0u);
+                const uint32_t ny = py + ((step & 2u) ? size : 0u);
+                const uint32_t nz = pz + ((step & 4u) ? size : 0u);
+                const uint32_t diff = (nx ^ px) | (ny ^ py) | (nz ^ pz);
+                const uint32_t h = 31u - __clz(diff);
+                if (h >= fr.K) return EV_END;  // left the frame's root cell
+                const uint32_t nsize = 1u << h;
+                const uint32_t keep = ~(nsize - 1u);
+                px = nx & keep;
+                py = ny & keep;
+                pz = nz & keep;
+                const uint32_t nlvl = fr.K - h;
+                if (nlvl < lvl) {
+                    const uint2 e = stk[(sbase + nlvl) * 64];
+                    pchild = e.x;
+                    pmask = e.y;
+                }
+                lvl = nlvl;
+                size = nsize;
+                tc0 = tc1;
+                eaxis = __ffs(step) - 1;
+                return EV_NONE;
+            };
+            uint32_t ev = EV_NONE;
+            uint32_t hit_id = 0, xf = 0;
+            float xf_tc1 = 0.f;
+            if (resume) {
+                // continue just past a transformed cell the walk came back from
+                resume = false;
+                const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
+                const float ey = fmaf((float)(py + size), fr.iy, fr.by);
+                const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
+                ev = advance(ex, ey, ez, min3f(ex, ey, ez));
+            }
+            // the hot loop: visit, descend or advance until something happens
+            while (ev == EV_NONE) {
+                if (++steps > a.step_limit) {
+                    ev = EV_LIMIT;
+                    break;
+                }
+                const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
+                const float ey = fmaf((float)(py + size), fr.iy, fr.by);
+                const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
+                const float tc1 = min3f(ex, ey, ez);
+                const uint32_t oct =
+                    (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
+                if ((pmask >> oct) & 1u) {
+                    const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
+                    // separate LDS and global reads (a select between the two
+                    // would become one generic load waiting on both counters)
+                    uint64_t wl = 0, wg = 0;
+                    if (n_lds) wl = lds_nodes[min(cidx, n_lds - 1u)];
+                    if (cidx >= n_lds) wg = gld(nodes, cidx);
+                    const uint64_t w = (cidx < n_lds) ? wl : wg;
+                    const uint32_t w0 = (uint32_t)w;
+                    const uint32_t w1 = (uint32_t)(w >> 32);
+                    const uint32_t cm = w0 & 0xFFu;
+                    if (cm == 0u) {
+                        ev = EV_HIT;
+                        hit_id = cidx;
+                        break;
+                    }
+                    if (!(w1 & kXform)) {
+                        stk[(sbase + lvl) * 64] = make_uint2(pchild, pmask);
+                        const uint32_t c24 = w0 >> 8;
+                        pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
+                        pmask = cm;
+                        ++lvl;
+                        size >>= 1;
+                        px += (fmaf((float)(px + size), fr.ix, fr.bx) <= tc0) ? size : 0u;
+                        py += (fmaf((float)(py + size), fr.iy, fr.by) <= tc0) ? size : 0u;
+                        pz += (fmaf((float)(pz + size), fr.iz, fr.bz) <= tc0) ? size : 0u;
+                        continue;
+                    }
+                    const uint32_t f = fbase + 1u + (w1 & 0x7FFFFFFFu);
+                    if (lds_frames[f].info & FR_INLINE) {
+                        ev = EV_ENTER;
+                        xf = f;
+                        xf_tc1 = tc1;
+                        break;
+                    }
+                    // a candidate frame: traced on its own, empty here
+                }
+                ev = advance(ex, ey, ez, tc1);
+            }
+            if (ev == EV_HIT) {
+                // the first solid leaf front to back ends this top-level frame
+                record_hit(tc0, hit_id, cur_f, eaxis);
+                mode = M_SELECT;
+                nest = 0;
+            } else if (ev == EV_LIMIT) {
+                best_id = kStepLimitId;
+                finish();
+            } else if (ev == EV_ENTER) {
+                const FrameRec& C = lds_frames[xf];
+                FrameRay cfr;
+                float t0;
+                int ea;
+                if (frame_setup(C, r, fminf(tl, xf_tc1), cfr, t0, ea)) {
+                    // save where the enclosing walk stands, then enter in place
+                    stk[(sbase + lvl) * 64] = make_uint2(pchild, pmask);
+                    fst[nest * 64] = make_uint4(cur_f | (lvl << 11) | (sbase << 16) | ((uint32_t)eaxis << 23), px, py, pz);
+                    ++nest;
+                    sbase += lvl;
+                    cur_f = xf;
+                    fr = cfr;
+                    pmask = C.info & FR_MASK;
+                    pchild = C.child;
+                    lvl = 1;
+                    size = 1u << (fr.K - 1);
+                    px = (fmaf((float)size, fr.ix, fr.bx) <= t0) ? size : 0u;
+                    py = (fmaf((float)size, fr.iy, fr.by) <= t0) ? size : 0u;
+                    pz = (fmaf((float)size, fr.iz, fr.bz) <= t0) ? size : 0u;
+                    tc0 = t0;
+                    eaxis = ea;
+                } else {
+                    resume = true;  // missed it: the cell is empty for this ray
+                }
+            } else {  // EV_END
+                if (nest > 0) {
+                    // back to the enclosing frame, just past the transformed cell
+                    --nest;
+                    const uint4 e = fst[nest * 64];
+                    cur_f = e.x & 0x7FFu;
+                    lvl = (e.x >> 11) & 31u;
+                    sbase = (e.x >> 16) & 127u;
+                    eaxis = (int)((e.x >> 23) & 3u);
+                    px = e.y;
+                    py = e.z;
+                    pz = e.w;
+                    float t0;
+                    int ea;
+                    frame_setup(lds_frames[cur_f], r, tl, fr, t0, ea);
+                    size = 1u << (fr.K - lvl);
+                    const uint2 sv = stk[(sbase + lvl) * 64];
+                    pchild = sv.x;
+                    pmask = sv.y;
+                    resume = true;
+                } else {
+                    mode = M_SELECT;
+                }
+            }
+        }
+        if (mode == M_SELECT) {
+            if (++steps > a.step_limit) {
+                best_id = kStepLimitId;
+                finish();
+                continue;
+            }
+            // ------------------------------------------------------ next candidate frame
+            if (a.sort_cand) {
+                float bc = INFINITY;
+                int pick = -1;
+                for (uint32_t c = 0; c < ncand; ++c) {
+                    // consumed and missed candidates hold +inf, which must never
+                    // pass the test even when tl is +inf (no hit yet, tmax = inf)
+                    const float e = ent[c * 64];
+                    if (e < INFINITY && e <= tl && (pick < 0 || e < bc)) {
+                        bc = e;
+                        pick = (int)c;
+                    }
+                }
+                if (pick < 0) {
+                    finish();
+                } else {
+                    ent[pick * 64] = INFINITY;
+                    if (start_frame(lds_cand[cbase + pick])) mode = M_WALK;
+                }
+            } else {
+                if (cnext >= ncand) {
+                    finish();
+                } else {
+                    const uint32_t f = lds_cand[cbase + cnext++];
+                    if (start_frame(f)) mode = M_WALK;
+                }
+            }
         }
     }
 
@@ -324,11 +506,12 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     }
 }
 
-size_t trace_lds_bytes(uint32_t lds_nodes, uint32_t n_frames, uint32_t stack_levels, uint32_t waves_per_block) {
-    return (size_t)lds_nodes * 8 + (size_t)n_frames * 64 + (size_t)waves_per_block * stack_levels * 64 * 8;
-}
-
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream) {
+    if (c.lds_bytes > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(trace_kernel, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
     return hipGetLastError();
 }

@@ -21,13 +21,13 @@ SVO_OK, SVO_EINVAL, SVO_ENOMEM, SVO_EDEVICE, SVO_ERANGE, SVO_EBUSY, SVO_ESTATE =
 NONE = 0xFFFFFFFF
 STEP_LIMIT = 0xFFFFFFFE
 MAX_DEPTH = 20
-MAX_SLOTS = 4096
-MAX_OVERFLOW = 64
+MAX_SLOTS = 1023
+MAX_INLINE_NEST = 4
 
 # every symbol include/svo.h declares
 EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
-           "svo_free_scene", "svo_scene_bytes", "svo_set_transforms", "svo_trace_rays", "svo_get_config",
-           "svo_set_config")
+           "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
+           "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays")
 
 
 class SvoError(RuntimeError):
@@ -40,6 +40,44 @@ class PoolInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_uint64), ("n_frames", ctypes.c_uint32), ("world_height", ctypes.c_uint32),
                 ("max_height", ctypes.c_uint32), ("max_nesting", ctypes.c_uint32), ("n_shared", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_uint32), ("fwd_3x4", ctypes.c_void_p), ("rays", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("out_id", ctypes.c_void_p), ("out_inst", ctypes.c_void_p),
+                ("out_t", ctypes.c_void_p), ("out_normal", ctypes.c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("forward", ctypes.c_float * 3), ("right", ctypes.c_float * 3),
+                ("up", ctypes.c_float * 3), ("tan_half_fov", ctypes.c_float), ("width", ctypes.c_uint32),
+                ("height", ctypes.c_uint32), ("samples", ctypes.c_uint32), ("seed", ctypes.c_uint32),
+                ("jitter", ctypes.c_uint32), ("tiled", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def make_camera(eye, target, up, vfov_deg, width, height, samples=1, seed=0, jitter=False, tiled=True) -> Camera:
+    """Camera record from eye / look-at / up (basis built in float64)."""
+    eye = np.asarray(eye, np.float64)
+    f = np.asarray(target, np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.asarray(up, np.float64))
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    c = Camera()
+    c.eye[:] = eye.astype(np.float32).tolist()
+    c.forward[:] = f.astype(np.float32).tolist()
+    c.right[:] = r.astype(np.float32).tolist()
+    c.up[:] = u.astype(np.float32).tolist()
+    c.tan_half_fov = float(np.tan(np.radians(vfov_deg) * 0.5))
+    c.width, c.height, c.samples, c.seed = int(width), int(height), int(samples), int(seed) & 0xFFFFFFFF
+    c.jitter, c.tiled = int(bool(jitter)), int(bool(tiled))
+    return c
+
+
+class SceneStats(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_uint32), ("n_frames", ctypes.c_uint32),
+                ("n_inline", ctypes.c_uint32), ("n_candidates", ctypes.c_uint32), ("stack_levels", ctypes.c_uint32),
+                ("nest_levels", ctypes.c_uint32)]
 
 
 class Config(ctypes.Structure):
@@ -72,8 +110,12 @@ def lib():
         "svo_upload": (I, [P, P, U64, U32, P, ctypes.c_float, U32, P, P, U32, ctypes.POINTER(U32)]),
         "svo_free_scene": (I, [P, U32]),
         "svo_scene_bytes": (I, [P, U32, ctypes.POINTER(U64)]),
+        "svo_get_scene_stats": (I, [P, U32, ctypes.POINTER(SceneStats)]),
         "svo_set_transforms": (I, [P, U32, U32, U32, P, P]),
         "svo_trace_rays": (I, [P, U32, P, U64, P, P, P, P, P]),
+        "svo_trace_batch": (I, [P, ctypes.POINTER(Job), U32, P]),
+        "svo_tune": (I, [P, U32, P, U64, P, ctypes.POINTER(Config)]),
+        "svo_generate_primary_rays": (I, [P, ctypes.POINTER(Camera), P, P]),
         "svo_get_config": (I, [P, ctypes.POINTER(Config)]),
         "svo_set_config": (I, [P, ctypes.POINTER(Config)]),
     }
@@ -189,6 +231,11 @@ class Context:
         _check(lib().svo_scene_bytes(self._ptr, int(scene), ctypes.byref(b)))
         return int(b.value)
 
+    def scene_stats(self, scene: int) -> SceneStats:
+        st = SceneStats()
+        _check(lib().svo_get_scene_stats(self._ptr, int(scene), ctypes.byref(st)))
+        return st
+
     def set_transforms(self, scene: int, fwd, first: int = 0, stream=None):
         f = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
         _check(lib().svo_set_transforms(self._ptr, int(scene), int(first), f.shape[0], _np_ptr(f),
@@ -200,6 +247,41 @@ class Context:
         _check(lib().svo_trace_rays(self._ptr, int(scene), rays.data_ptr(), n, out_id.data_ptr(),
                                     None if out_inst is None else out_inst.data_ptr(), out_t.data_ptr(),
                                     None if out_normal is None else out_normal.data_ptr(), _stream_handle(stream)))
+
+    def tune(self, scene: int, sample_rays, stream=None) -> Config:
+        """Autotune the kernel configuration for `scene` on device sample rays."""
+        c = Config()
+        _check(lib().svo_tune(self._ptr, int(scene), sample_rays.data_ptr(), sample_rays.shape[0],
+                              _stream_handle(stream), ctypes.byref(c)))
+        return c
+
+    def primary_rays(self, cam: Camera, out=None, stream=None):
+        """Generate cam.width * cam.height * cam.samples rays into a device tensor [n, 8]."""
+        import torch
+        n = cam.width * cam.height * cam.samples
+        if out is None:
+            out = torch.empty((n, 8), dtype=torch.float32, device="cuda:%d" % self.device)
+        if out.shape[0] < n:
+            raise ValueError("output buffer too small")
+        _check(lib().svo_generate_primary_rays(self._ptr, ctypes.byref(cam), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def trace_batch(self, jobs, stream=None):
+        """jobs: sequence of dicts with keys scene, rays (device [n, 8]), out_id,
+        out_t, and optionally out_inst, out_normal, fwd (host [n_slots, 12])."""
+        arr = (Job * max(len(jobs), 1))()
+        keep = []
+        for i, j in enumerate(jobs):
+            fwd = j.get("fwd")
+            if fwd is not None:
+                fwd = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
+                keep.append(fwd)
+            r = j["rays"]
+            arr[i] = Job(int(j["scene"]), _np_ptr(fwd) if fwd is not None else None, r.data_ptr(), r.shape[0],
+                         j["out_id"].data_ptr(), j["out_inst"].data_ptr() if j.get("out_inst") is not None else None,
+                         j["out_t"].data_ptr(),
+                         j["out_normal"].data_ptr() if j.get("out_normal") is not None else None)
+        _check(lib().svo_trace_batch(self._ptr, arr, len(jobs), _stream_handle(stream)))
 
     def trace(self, scene: int, rays, stream=None, normals: bool = True) -> Hits:
         import torch

@@ -54,7 +54,7 @@ def _check_scene(ctx, torch, sc, rays, frame=0, static=False, fwd=None, max_rate
     finally:
         ctx.free_scene(h)
     ref = oracle.trace_scene(sc, rays, frame=frame, static=static, fwd=fwd, margin=True)
-    st = parity.compare(g, ref, ref.margin)
+    st = parity.compare(g, ref, ref.margin, rays)
     _say(label or sc.name, st)
     parity.assert_parity(st, max_rate)
     return st
@@ -125,7 +125,7 @@ def test_terrain1024_full_resolution_sampled(ctx, torch_dev):
     finally:
         ctx.free_scene(h)
     ref = oracle.trace_scene(sc, rays[idx], frame=30, margin=True)
-    st = parity.compare(tuple(a[idx] for a in g), ref, ref.margin)
+    st = parity.compare(tuple(a[idx] for a in g), ref, ref.margin, rays[idx])
     _say("terrain1024-1080p-sampled", st)
     parity.assert_parity(st, 1e-4)
 
@@ -142,7 +142,7 @@ def test_far_pointers(ctx, torch_dev):
         ctx.free_scene(h)
     ref = oracle.trace(far, sc.root, sc.root_min, sc.root_size, sc.slot_child, sc.slot_cell, sc.xform(0), rays,
                        margin=True)
-    parity.assert_parity(parity.compare(g, ref, ref.margin))
+    parity.assert_parity(parity.compare(g, ref, ref.margin, rays))
 
 
 def test_degenerate_rays_and_worlds(ctx, torch_dev):
@@ -180,7 +180,7 @@ def test_degenerate_rays_and_worlds(ctx, torch_dev):
         ctx.free_scene(h)
     ref = oracle.trace(leaf, 0, np.zeros(3), 16.0, np.zeros(0, np.uint32), np.zeros((0, 4)), np.zeros((0, 12)), rays,
                        margin=True)
-    parity.assert_parity(parity.compare(g, ref, ref.margin))
+    parity.assert_parity(parity.compare(g, ref, ref.margin, rays))
 
 
 def test_zero_rays_and_repeated_launches(ctx, torch_dev):
@@ -222,4 +222,134 @@ def test_transform_updates_are_stream_ordered(ctx, torch_dev):
         ctx.free_scene(h)
     for f, hh in zip((3, 4, 5), res):
         ref = oracle.trace_scene(sc, rays, frame=f, margin=True)
-        parity.assert_parity(parity.compare(parity.to_numpy(hh), ref, ref.margin))
+        parity.assert_parity(parity.compare(parity.to_numpy(hh), ref, ref.margin, rays))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_inline_contained_frames(ctx, torch_dev, seed):
+    """Shrunk, rotated subtrees stay inside their static cells: the walk
+    enters them in place (nested chains included), no candidate frames."""
+    sc = S.tiny_scene(seed, K=5, n_slots=4, nested=True, scale_range=(0.3, 0.55))
+    rays = S.random_rays(seed + 3, 4000, 0.0, sc.root_size)
+    h = ctx.upload_scene(sc)
+    try:
+        ctx.set_transforms(h, sc.xform(0))
+        st = ctx.scene_stats(h)
+        _say("inline stats", dict(n_inline=st.n_inline, n_cand=st.n_candidates, nest=st.nest_levels,
+                                  stack=st.stack_levels))
+        assert st.n_inline == sc.n_slots and st.n_candidates == 0 and st.nest_levels >= 2
+        g = _trace(ctx, torch_dev, h, rays)
+    finally:
+        ctx.free_scene(h)
+    ref = oracle.trace_scene(sc, rays, margin=True)
+    stt = parity.compare(g, ref, ref.margin, rays)
+    if stt["worst_t"]:
+        stt["worst_t"]["ray_data"] = rays[stt["worst_t"]["ray"]].tolist()
+    _say("inline-%d" % seed, stt)
+    parity.assert_parity(stt)
+    assert (ref.inst[ref.id != NONE] != NONE).sum() > 10
+
+
+def test_inline_and_candidates_mixed(ctx, torch_dev):
+    """Per slot: contained ones in place, overflowing ones as candidates."""
+    sc = S.tiny_scene(7, K=5, n_slots=4, nested=True, scale_range=(0.3, 1.6), translate=0.2)
+    rays = S.random_rays(70, 4000, 0.0, sc.root_size)
+    h = ctx.upload_scene(sc)
+    try:
+        seen_inline = seen_cand = 0
+        for k in range(6):
+            fwd = sc.xform(0).copy()
+            # shrink a different subset of slots each time
+            for s in range(sc.n_slots):
+                if (k >> (s % 3)) & 1:
+                    A = fwd[s].reshape(3, 4).astype(np.float64)
+                    c = sc.slot_cell[s, :3].astype(np.float64) + sc.slot_cell[s, 3] / 2
+                    L = A[:, :3] * (0.3 / np.abs(np.linalg.det(A[:, :3])) ** (1 / 3))
+                    fwd[s] = xf.to_f32(xf.about_pivot(L, c)).reshape(12)
+            ctx.set_transforms(h, fwd)
+            st = ctx.scene_stats(h)
+            seen_inline += st.n_inline
+            seen_cand += st.n_candidates
+            g = _trace(ctx, torch_dev, h, rays)
+            ref = oracle.trace_scene(sc, rays, fwd=fwd, margin=True)
+            stt = parity.compare(g, ref, ref.margin, rays)
+            _say("mixed-%d" % k, dict(n_inline=st.n_inline, n_cand=st.n_candidates), stt)
+            parity.assert_parity(stt)
+    finally:
+        ctx.free_scene(h)
+    assert seen_inline > 0 and seen_cand > 0
+
+
+def _outs(torch, n):
+    return dict(out_id=torch.empty(n, dtype=torch.int32, device="cuda"),
+                out_inst=torch.empty(n, dtype=torch.int32, device="cuda"),
+                out_t=torch.empty(n, dtype=torch.float32, device="cuda"),
+                out_normal=torch.empty((n, 3), dtype=torch.float32, device="cuda"))
+
+
+def test_batch_equals_alone(ctx, torch_dev):
+    """Rays of several requests, scenes and animation frames in one launch:
+    every job's result is bit-identical to tracing it alone."""
+    torch = torch_dev
+    sph = S.noisy_sphere_d6()
+    ter = S.fbm_terrain_d10()
+    tin = S.tiny_scene(3, K=5, n_slots=4, nested=True, scale_range=(0.3, 1.5))
+    hs = {k: ctx.upload_scene(v) for k, v in (("sph", sph), ("ter", ter), ("tin", tin))}
+    try:
+        ctx.set_transforms(hs["sph"], sph.xform(0))
+        ctx.set_transforms(hs["tin"], tin.xform(0))
+        ctx.set_transforms(hs["ter"], ter.xform(5))
+        specs = [("sph", sph.rays(W=100, H=77)[0], None),
+                 ("ter", ter.rays(W=160, H=90)[0], None),            # scene's current transforms (frame 5)
+                 ("ter", ter.rays(W=123, H=45)[0], ter.xform(33)),    # a different animation frame
+                 ("tin", S.random_rays(4, 3001, 0.0, 32.0), None),
+                 ("sph", sph.rays(W=8, H=1)[0], None)]
+        jobs = []
+        for name, rays, fwd in specs:
+            r = torch.from_numpy(rays).cuda()
+            j = dict(scene=hs[name], rays=r, fwd=fwd, **_outs(torch, rays.shape[0]))
+            jobs.append(j)
+        ctx.trace_batch(jobs)
+        torch.cuda.synchronize()
+        for (name, rays, fwd), j in zip(specs, jobs):
+            if fwd is not None:
+                ctx.set_transforms(hs[name], fwd)
+            alone = ctx.trace(hs[name], j["rays"])
+            torch.cuda.synchronize()
+            if fwd is not None:
+                ctx.set_transforms(hs[name], ter.xform(5))
+            assert torch.equal(alone.id, j["out_id"]), name
+            assert torch.equal(alone.inst, j["out_inst"]), name
+            assert torch.equal(alone.t, j["out_t"]), name
+            assert torch.equal(alone.normal, j["out_normal"]), name
+        # and against the oracle for the job with its own transforms
+        ref = oracle.trace_scene(ter, specs[2][1], fwd=specs[2][2], margin=True)
+        g = (jobs[2]["out_id"].cpu().numpy().view(np.uint32), jobs[2]["out_inst"].cpu().numpy().view(np.uint32),
+             jobs[2]["out_t"].cpu().numpy().astype(np.float64), jobs[2]["out_normal"].cpu().numpy().astype(np.float64))
+        parity.assert_parity(parity.compare(g, ref, ref.margin, specs[2][1]))
+    finally:
+        for h in hs.values():
+            ctx.free_scene(h)
+
+
+def test_results_independent_of_kernel_config(ctx, torch_dev):
+    torch = torch_dev
+    sc = S.fbm_terrain_d10()
+    rays, _ = sc.rays(W=320, H=180)
+    r = torch.from_numpy(rays).cuda()
+    h = ctx.upload_scene(sc)
+    base_cfg = ctx.get_config().as_dict()
+    try:
+        ctx.set_transforms(h, sc.xform(9))
+        ref = ctx.trace(h, r)
+        torch.cuda.synchronize()
+        for cfg in (dict(waves_per_block=1, blocks_per_cu=1, lds_cache_nodes=0, refill_lanes=0),
+                    dict(waves_per_block=8, blocks_per_cu=2, lds_cache_nodes=4096, refill_lanes=16),
+                    dict(waves_per_block=2, blocks_per_cu=8, lds_cache_nodes=512, refill_lanes=1)):
+            ctx.set_config(**cfg)
+            o = ctx.trace(h, r)
+            torch.cuda.synchronize()
+            assert torch.equal(o.id, ref.id) and torch.equal(o.t, ref.t) and torch.equal(o.normal, ref.normal), cfg
+    finally:
+        ctx.set_config(**base_cfg)
+        ctx.free_scene(h)
