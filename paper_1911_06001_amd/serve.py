@@ -1,0 +1,285 @@
+"""Serving loop: render requests of uneven resolution and scene, continuously
+batched into persistent trace launches, admitted by device-memory footprint.
+
+Each request asks for one frame (an animation frame index) of one resident
+scene at some resolution and rays per pixel.  Pools and transform tables stay
+resident; a request only brings its ray and output buffers.
+
+  batched  requests are admitted while their footprint fits the budget;
+           every step packs up to `max_rays_per_step` rays from the admitted
+           requests (first come, first served; large requests are split
+           across steps) into one svo_trace_batch launch, each job with its
+           own scene and animation frame; two steps are kept in flight so the
+           host prepares step k+1 while the device runs step k.
+  single   the baseline: one request per svo_trace_rays launch, first come,
+           first served, the next one starting when the previous finished.
+
+Latency = completion - arrival, with completion read from device events on
+the launch stream (the device clock, aligned with the host clock at start).
+The loop itself is host Python; every step of the trace runs in libsvo.so.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from . import svo
+
+RAY_BYTES = 32
+OUT_BYTES = 4 + 4 + 4 + 12  # id, inst, t, normal
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float      # seconds after the start of the run
+    scene: str
+    frame: int
+    width: int
+    height: int
+    samples: int
+    seed: int = 0
+
+    @property
+    def rays(self) -> int:
+        return self.width * self.height * self.samples
+
+    @property
+    def footprint(self) -> int:
+        return self.rays * (RAY_BYTES + OUT_BYTES)
+
+
+@dataclass
+class SceneEntry:
+    handle: int
+    xform: Callable[[int], np.ndarray]   # frame -> [n_slots, 12] forward maps
+    camera: dict
+
+
+@dataclass
+class Result:
+    req: Request
+    admitted: float = 0.0
+    completed: float = 0.0
+    out: Optional[dict] = None           # device tensors, kept when keep_outputs
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.req.arrival
+
+
+@dataclass
+class _Active:
+    req: Request
+    res: Result
+    rays: "object"
+    out: dict
+    fwd: np.ndarray
+    next_ray: int = 0        # first ray not yet submitted
+    pending_chunks: int = 0  # submitted chunks not yet complete
+
+
+class Scheduler:
+    """The batching policy, free of device calls (so it can be tested alone).
+
+    admit(): move waiting requests (first come, first served) into the
+    active set while their footprint fits the budget.  plan(): pick the next
+    step's chunks, up to `max_rays` rays, oldest admitted request first.
+    """
+
+    def __init__(self, budget: int, max_rays: int):
+        self.budget = int(budget)
+        self.max_rays = int(max_rays)
+        self.used = 0
+        self.max_used = 0
+
+    def admit(self, waiting: "collections.deque", on_admit: Callable[[Request], object]) -> list:
+        admitted = []
+        while waiting and self.used + waiting[0].footprint <= self.budget:
+            req = waiting.popleft()
+            self.used += req.footprint
+            self.max_used = max(self.max_used, self.used)
+            admitted.append(on_admit(req))
+        if waiting and waiting[0].footprint > self.budget:
+            raise ValueError("request %d needs %d bytes, more than the budget %d" %
+                             (waiting[0].rid, waiting[0].footprint, self.budget))
+        return admitted
+
+    def release(self, req: Request):
+        self.used -= req.footprint
+
+    def plan(self, active: list) -> list:
+        """[(active, lo, hi)] covering at most max_rays rays; advances next_ray."""
+        chunks, left = [], self.max_rays
+        for a in active:
+            if left <= 0:
+                break
+            todo = a.req.rays - a.next_ray
+            if todo <= 0:
+                continue
+            k = min(todo, left)
+            chunks.append((a, a.next_ray, a.next_ray + k))
+            a.next_ray += k
+            a.pending_chunks += 1
+            left -= k
+        return chunks
+
+
+def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: int = 60,
+                     resolutions=((256, 256), (1280, 720), (1920, 1080), (2048, 1152)),
+                     samples=(1, 5)) -> List[Request]:
+    """Seeded Poisson arrival trace with uniformly drawn scene, frame,
+    resolution and rays per pixel."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        W, H = resolutions[rng.integers(0, len(resolutions))]
+        out.append(Request(i, float(t[i]), scenes[rng.integers(0, len(scenes))], int(rng.integers(0, frames)),
+                           int(W), int(H), int(rng.integers(samples[0], samples[1] + 1)), int(rng.integers(0, 2**31))))
+    return out
+
+
+class Server:
+    def __init__(self, ctx: svo.Context, scenes: Dict[str, SceneEntry], hbm_budget: int,
+                 max_rays_per_step: int = 1 << 22, inflight_steps: int = 2, keep_outputs: bool = False):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.scenes = scenes
+        self.budget = int(hbm_budget)
+        self.max_rays = int(max_rays_per_step)
+        self.inflight_steps = int(inflight_steps)
+        self.keep = keep_outputs
+        self.stream = torch.cuda.current_stream()
+        self.dev = torch.device("cuda:%d" % ctx.device)
+
+    # -- helpers
+    def _camera(self, req: Request):
+        c = self.scenes[req.scene].camera
+        return svo.make_camera(c["eye"], c["target"], c["up"], c["fov"], req.width, req.height, samples=req.samples,
+                               seed=req.seed, jitter=req.samples > 1, tiled=True)
+
+    def _buffers(self, n: int):
+        t = self.torch
+        return dict(out_id=t.empty(n, dtype=t.int32, device=self.dev), out_inst=t.empty(n, dtype=t.int32, device=self.dev),
+                    out_t=t.empty(n, dtype=t.float32, device=self.dev),
+                    out_normal=t.empty((n, 3), dtype=t.float32, device=self.dev))
+
+    def run(self, requests: List[Request], mode: str = "batched") -> List[Result]:
+        if mode == "batched":
+            return self._run_batched(requests)
+        if mode == "single":
+            return self._run_single(requests)
+        raise ValueError(mode)
+
+    # -- continuous batching
+    def _run_batched(self, requests: List[Request]) -> List[Result]:
+        t = self.torch
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = collections.deque()
+        active: List[_Active] = []
+        inflight = collections.deque()   # (event, [(active, n_rays)])
+        results: List[Result] = []
+        sched = Scheduler(self.budget, self.max_rays)
+        self.scheduler = sched
+        t.cuda.synchronize()
+        start_ev = t.cuda.Event(enable_timing=True)
+        start_ev.record(self.stream)
+        t0 = time.perf_counter()
+
+        def on_admit(req):
+            entry = self.scenes[req.scene]
+            rays = self.ctx.primary_rays(self._camera(req), stream=self.stream)
+            res = Result(req, admitted=time.perf_counter() - t0)
+            a = _Active(req, res, rays, self._buffers(req.rays), np.ascontiguousarray(entry.xform(req.frame), np.float32))
+            active.append(a)
+            return a
+
+        while pending or waiting or active or inflight:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # retire finished steps (in stream order)
+            while inflight and inflight[0][0].query():
+                ev, chunks = inflight.popleft()
+                done_at = start_ev.elapsed_time(ev) * 1e-3
+                for a, _, _ in chunks:
+                    a.pending_chunks -= 1
+                    if a.pending_chunks == 0 and a.next_ray >= a.req.rays:
+                        a.res.completed = done_at
+                        if self.keep:
+                            a.res.out = a.out
+                            a.res.out["rays"] = a.rays
+                        results.append(a.res)
+                        active.remove(a)
+                        sched.release(a.req)
+            sched.admit(waiting, on_admit)
+            # submit one step when a slot is free and there is work
+            if len(inflight) < self.inflight_steps:
+                chunks = sched.plan(active)
+                if chunks:
+                    jobs = [dict(scene=self.scenes[a.req.scene].handle, fwd=a.fwd, rays=a.rays[lo:hi],
+                                 out_id=a.out["out_id"][lo:hi], out_inst=a.out["out_inst"][lo:hi],
+                                 out_t=a.out["out_t"][lo:hi], out_normal=a.out["out_normal"][lo:hi])
+                            for a, lo, hi in chunks]
+                    self.ctx.trace_batch(jobs, stream=self.stream)
+                    ev = t.cuda.Event(enable_timing=True)
+                    ev.record(self.stream)
+                    inflight.append((ev, chunks))
+                    continue
+            # nothing to submit: wait for the device or the next arrival
+            if inflight:
+                if not (pending and pending[0].arrival <= time.perf_counter() - t0):
+                    time.sleep(0)
+            elif pending and not waiting:
+                dt = pending[0].arrival - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(min(dt, 0.001))
+        t.cuda.synchronize()
+        return sorted(results, key=lambda r: r.req.rid)
+
+    # -- one request per launch
+    def _run_single(self, requests: List[Request]) -> List[Result]:
+        t = self.torch
+        queue = sorted(requests, key=lambda r: r.arrival)
+        results = []
+        t.cuda.synchronize()
+        start_ev = t.cuda.Event(enable_timing=True)
+        start_ev.record(self.stream)
+        t0 = time.perf_counter()
+        for req in queue:
+            now = time.perf_counter() - t0
+            if req.arrival > now:
+                time.sleep(req.arrival - now)
+            entry = self.scenes[req.scene]
+            res = Result(req, admitted=time.perf_counter() - t0)
+            rays = self.ctx.primary_rays(self._camera(req), stream=self.stream)
+            out = self._buffers(req.rays)
+            self.ctx.set_transforms(entry.handle, entry.xform(req.frame), stream=self.stream)
+            self.ctx.trace_into(entry.handle, rays, out["out_id"], out["out_t"], out["out_inst"], out["out_normal"],
+                                stream=self.stream)
+            ev = t.cuda.Event(enable_timing=True)
+            ev.record(self.stream)
+            ev.synchronize()
+            res.completed = start_ev.elapsed_time(ev) * 1e-3
+            if self.keep:
+                out["rays"] = rays
+                res.out = out
+            results.append(res)
+        return sorted(results, key=lambda r: r.req.rid)
+
+
+def summarize(results: List[Result]) -> dict:
+    lat = np.array([r.latency for r in results]) * 1e3
+    rays = sum(r.req.rays for r in results)
+    span = max(r.completed for r in results) - min(r.req.arrival for r in results)
+    return dict(requests=len(results), p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3), mean_ms=round(float(lat.mean()), 3),
+                mrays_per_s=round(rays / span / 1e6, 2) if span > 0 else None, rays=int(rays),
+                makespan_s=round(span, 4))

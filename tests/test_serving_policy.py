@@ -1,0 +1,74 @@
+"""The serving loop's batching policy on the host (no device): admission never
+exceeds the budget and is first come first served, steps cover every ray of
+every admitted request exactly once, a request larger than the budget is
+rejected."""
+import collections
+
+import numpy as np
+import pytest
+
+from paper_1911_06001_amd.serve import Request, Scheduler, _Active, Result, poisson_requests
+
+
+def _sim(reqs, budget, max_rays, finish_after=2, seed=0):
+    """Drive the scheduler with a fake executor: a step completes
+    `finish_after` plans after it was issued."""
+    rng = np.random.default_rng(seed)
+    s = Scheduler(budget, max_rays)
+    waiting = collections.deque(reqs)
+    active, inflight, order, done = [], collections.deque(), [], []
+    covered = {r.rid: np.zeros(r.rays, np.int32) for r in reqs}
+    while waiting or active or inflight:
+        def on_admit(req):
+            a = _Active(req, Result(req), None, {}, None)
+            active.append(a)
+            order.append(req.rid)
+            return a
+        s.admit(waiting, on_admit)
+        assert s.used <= budget
+        chunks = s.plan(active)
+        for a, lo, hi in chunks:
+            assert hi - lo > 0
+            covered[a.req.rid][lo:hi] += 1
+        assert sum(hi - lo for _, lo, hi in chunks) <= max_rays
+        if chunks:
+            inflight.append(chunks)
+        if inflight and (len(inflight) >= finish_after or not chunks or rng.random() < 0.3):
+            for a, lo, hi in inflight.popleft():
+                a.pending_chunks -= 1
+                if a.pending_chunks == 0 and a.next_ray >= a.req.rays:
+                    active.remove(a)
+                    s.release(a.req)
+                    done.append(a.req.rid)
+    return s, order, done, covered
+
+
+def test_budget_fifo_and_exact_coverage():
+    reqs = poisson_requests(60, 1000.0, 4, ["a", "b"], resolutions=((16, 16), (40, 30), (64, 48)), samples=(1, 3))
+    budget = max(r.footprint for r in reqs) * 3
+    s, order, done, covered = _sim(reqs, budget, max_rays=5000)
+    assert order == sorted(order)                      # admitted first come first served
+    assert sorted(done) == [r.rid for r in reqs]      # everything finished
+    assert all((c == 1).all() for c in covered.values())   # each ray submitted exactly once
+    assert s.max_used <= budget and s.used == 0
+
+
+def test_small_steps_split_large_requests():
+    reqs = [Request(i, 0.0, "a", 0, 100, 100, 2) for i in range(3)]
+    s, order, done, covered = _sim(reqs, budget=10**9, max_rays=777)
+    assert all((c == 1).all() for c in covered.values())
+
+
+def test_oversized_request_is_rejected():
+    big = Request(0, 0.0, "a", 0, 1000, 1000, 5)
+    s = Scheduler(budget=big.footprint - 1, max_rays=1 << 20)
+    with pytest.raises(ValueError):
+        s.admit(collections.deque([big]), lambda r: r)
+
+
+def test_poisson_trace_is_seeded():
+    a = poisson_requests(50, 100.0, 7, ["x", "y"])
+    b = poisson_requests(50, 100.0, 7, ["x", "y"])
+    assert [(r.arrival, r.scene, r.width, r.samples) for r in a] == [(r.arrival, r.scene, r.width, r.samples) for r in b]
+    gaps = np.diff([r.arrival for r in a])
+    assert (gaps >= 0).all() and 0.003 < gaps.mean() < 0.03
