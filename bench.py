@@ -82,6 +82,48 @@ def cpu_baseline(scene, rays, frames, budget_s):
     return dict(rays=done, seconds=spent, threads=threads, frames=frame_list, bytes_per_ray=bytes_sum / max(done, 1))
 
 
+def instances_throughput(ctx, steps):
+    """Instanced scene (64 DAG-shared instances of 4 SVOs in a 4096^3 world):
+    1080p primary rays, then 4 cosine-weighted AO rays per pixel from the
+    primary hits (incoherent).  Mrays/s of each trace, kernel time from HIP
+    events on the launch stream."""
+    import torch
+    from svogen import scenes
+    t0 = time.perf_counter()
+    sc = scenes.instanced_scene()
+    log("instanced scene: %d nodes (%.1f s)" % (sc.nodes.shape[0], time.perf_counter() - t0))
+    h = ctx.upload_scene(sc)
+    ctx.set_transforms(h, sc.xform(0))
+    rays_np, _ = sc.rays()
+    rays = torch.from_numpy(rays_np).cuda()
+    n = rays.shape[0]
+    prim = ctx.trace(h, rays)
+    ao = ctx.ao_rays(rays, prim, k=4, seed=3, radius=64.0)
+    ctx.tune(h, rays)
+    out_ao = ctx.trace(h, ao)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, r, out in (("primary", rays, prim), ("ao", ao, out_ao)):
+        for _ in range(2):
+            ctx.trace_into(h, r, out.id, out.t, out.inst, out.normal, stream=stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in evs:
+            a.record(stream)
+            ctx.trace_into(h, r, out.id, out.t, out.inst, out.normal, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        res[name] = {"rays": int(r.shape[0]), "kernel_ms": round(ms, 4), "mrays_per_s": round(r.shape[0] / ms / 1e3, 2)}
+    st = ctx.scene_stats(h)
+    ctx.free_scene(h)
+    log("instances: primary %.0f Mrays/s, AO %.0f Mrays/s" % (res["primary"]["mrays_per_s"], res["ao"]["mrays_per_s"]))
+    res.update({"workload": "instances4096: 64 instances (sphere d8, noise blob d9, heightfield d10, box lattice d11) "
+                            "at levels 1-3 of a 4096^3 world; 1920x1080 primary + 4 AO rays per pixel",
+                "nodes": int(sc.nodes.shape[0]), "candidates": int(st.n_candidates), "inline": int(st.n_inline)})
+    return res
+
+
 def serve_latency(ctx, terrain, terrain_handle, n_requests, load):
     """p50/p99 frame latency of a Poisson request stream over the noisy-sphere
     and terrain scenes (resolutions 256^2 .. 2048x1152, 1-5 rays per pixel),
@@ -130,6 +172,7 @@ def main():
                     help="requests in the served-latency run (0 disables)")
     ap.add_argument("--serve-load", type=float, default=0.6, help="offered load as a fraction of saturation")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--no-instances", action="store_true", help="skip the instanced-scene measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -252,6 +295,9 @@ def main():
                 "bytes_per_ray": round(bytes_per_ray, 2), "rays_per_launch": n,
                 "kernel_ms": round(kmean_a * 1e3, 4)}
 
+    instances = None
+    if not args.no_instances:
+        instances = instances_throughput(ctx, max(5, K // 6))
     serving = None
     if args.serve_requests > 0:
         serving = serve_latency(ctx, sc, anim, args.serve_requests, args.serve_load)
@@ -281,6 +327,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "instances": instances,
     }
     ctx.free_scene(anim)
     ctx.free_scene(stat)

@@ -259,6 +259,17 @@ typedef struct {
    consecutive. */
 int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream);
 
+/* Ambient-occlusion rays from primary hits: for each of the n primary rays
+   (device, 8 floats each) with hit t (device, n floats) and normal (device,
+   n * 3 floats) as svo_trace_rays returns them, write k rays to out_rays
+   (device, n * k * 8 floats, 16-byte aligned): origin p + offset *
+   max(1, |p|inf) * normal with p = o + t d, a cosine-weighted direction
+   about the normal (seeded, counter-based: ray (i, j) depends only on seed,
+   i and j), tmin = 0, tmax = radius.  A primary miss or a start inside a
+   voxel (zero normal) yields k rays with tmin > tmax, which trace as misses. */
+int svo_generate_ao_rays(svo_ctx* ctx, const float* rays, const float* t, const float* normal, uint64_t n, uint32_t k,
+                         uint32_t seed, float radius, float offset, float* out_rays, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

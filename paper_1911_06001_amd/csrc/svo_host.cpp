@@ -362,6 +362,16 @@ Scene* find_scene(svo_ctx* ctx, svo_scene h) {
     return it == ctx->scenes.end() ? nullptr : it->second.get();
 }
 
+// Layout of a scene's frame table: n_frames records, then the candidate list
+// (n_slots u32), then one bounding sphere (centre xyz, radius) per record.
+inline size_t cand_offset(uint32_t n_frames) { return (size_t)n_frames * sizeof(svo::FrameRec); }
+inline size_t sphere_offset(uint32_t n_frames, uint32_t n_slots) {
+    return (cand_offset(n_frames) + (size_t)n_slots * sizeof(uint32_t) + 15) & ~(size_t)15;
+}
+inline size_t table_size(uint32_t n_frames, uint32_t n_slots) {
+    return sphere_offset(n_frames, n_slots) + (size_t)n_frames * 16;
+}
+
 struct TableInfo {
     uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0;
 };
@@ -374,7 +384,8 @@ struct TableInfo {
 int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out, TableInfo& T) {
     const Analysis& A = S.an;
     svo::FrameRec* rec = reinterpret_cast<svo::FrameRec*>(out);
-    uint32_t* cand = reinterpret_cast<uint32_t*>(out + (size_t)S.n_frames * sizeof(svo::FrameRec));
+    uint32_t* cand = reinterpret_cast<uint32_t*>(out + cand_offset(S.n_frames));
+    float* sph = reinterpret_cast<float*>(out + sphere_offset(S.n_frames, S.n_slots));
     std::memset(out, 0, S.table_bytes);
     T = TableInfo();
     // world
@@ -419,6 +430,27 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
         F.info = A.slot_mask[s] | (K << svo::FR_K_SHIFT);
         F.inst = s;
         F.root = A.slot_node[s];
+        {
+            // world-space bounding sphere of the moved root cell (Sec. 4.1):
+            // the image of the cell centre and the farthest image corner
+            double c[3], h = 0.5 * cell[3];
+            for (int r = 0; r < 3; ++r)
+                c[r] = world[s].m[r][0] * (cell[0] + h) + world[s].m[r][1] * (cell[1] + h) +
+                       world[s].m[r][2] * (cell[2] + h) + world[s].m[r][3];
+            double rad = 0.0;
+            for (int k = 0; k < 8; ++k) {
+                double q = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    const double v = world[s].m[r][0] * (cell[0] + (((k >> 0) & 1) ? cell[3] : 0.0)) +
+                                     world[s].m[r][1] * (cell[1] + (((k >> 1) & 1) ? cell[3] : 0.0)) +
+                                     world[s].m[r][2] * (cell[2] + (((k >> 2) & 1) ? cell[3] : 0.0)) + world[s].m[r][3];
+                    q += (v - c[r]) * (v - c[r]);
+                }
+                rad = std::max(rad, std::sqrt(q));
+            }
+            for (int r = 0; r < 3; ++r) sph[4 * (1 + s) + r] = (float)c[r];
+            sph[4 * (1 + s) + 3] = (float)rad;
+        }
         // does the moved cell stay inside its static cell (parent frame)?
         double pmin[3], psize;
         if (p < 0) {
@@ -586,7 +618,7 @@ int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t r
             return fail(SVO_ENOMEM, "device allocation of %zu bytes failed", nb);
         }
         S->n_frames = 1 + n_slots;
-        S->table_bytes = (size_t)S->n_frames * sizeof(svo::FrameRec) + (size_t)n_slots * sizeof(uint32_t) + 16;
+        S->table_bytes = table_size(S->n_frames, n_slots);
         const size_t fb = S->table_bytes;
         for (int k = 0; k < 2; ++k) {
             if (hipMalloc((void**)&S->d_table[k], fb) != hipSuccess ||
@@ -772,7 +804,8 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     a.job0 = svo::JobRec{S->d_nodes, reinterpret_cast<const float4*>(rays), out_id, out_inst, out_t, out_normal,
                          0, 0, 0, S->n_cand, cache};
     a.frames = reinterpret_cast<const svo::FrameRec*>(S->d_table[S->cur]);
-    a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + (size_t)S->n_frames * sizeof(svo::FrameRec));
+    a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + cand_offset(S->n_frames));
+    a.spheres = reinterpret_cast<const float4*>(S->d_table[S->cur] + sphere_offset(S->n_frames, S->n_slots));
     a.n_jobs = 1;
     a.n_frames = S->n_frames;
     a.n_cand_total = S->n_cand;
@@ -864,7 +897,8 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         // pack [jobs][frames][candidates]
         const size_t jb = plan.size() * sizeof(svo::JobRec);
         const size_t fb = (size_t)frames * sizeof(svo::FrameRec);
-        const size_t bytes = jb + fb + (size_t)cands * sizeof(uint32_t) + 16;
+        const size_t sb = (jb + fb + (size_t)cands * sizeof(uint32_t) + 15) & ~(size_t)15;
+        const size_t bytes = sb + (size_t)frames * 16;
         auto& B = ctx->batch[ctx->next_batch];
         ctx->next_batch = (ctx->next_batch + 1) % 4;
         if (B.ev) HIP_TRY(hipEventSynchronize(B.ev));
@@ -883,6 +917,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         svo::JobRec* jr = reinterpret_cast<svo::JobRec*>(B.host);
         svo::FrameRec* fr = reinterpret_cast<svo::FrameRec*>(B.host + jb);
         uint32_t* cr = reinterpret_cast<uint32_t*>(B.host + jb + fb);
+        float* sr = reinterpret_cast<float*>(B.host + sb);
         uint64_t begin = 0;
         svo::TraceArgs a{};
         uint32_t max_cand = 0;
@@ -891,7 +926,8 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
             Scene& S = *P.S;
             const unsigned char* tab = P.table.empty() ? S.h_stage[S.cur] : P.table.data();
             std::memcpy(fr + P.frame_base, tab, (size_t)S.n_frames * sizeof(svo::FrameRec));
-            const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + (size_t)S.n_frames * sizeof(svo::FrameRec));
+            std::memcpy(sr + 4 * (size_t)P.frame_base, tab + sphere_offset(S.n_frames, S.n_slots), (size_t)S.n_frames * 16);
+            const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + cand_offset(S.n_frames));
             for (uint32_t c = 0; c < P.T.n_cand; ++c) cr[P.cand_base + c] = P.frame_base + sc[c];
             const svo_job& J = *P.j;
             jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
@@ -905,6 +941,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         a.jobs = reinterpret_cast<const svo::JobRec*>(B.dev);
         a.frames = reinterpret_cast<const svo::FrameRec*>(B.dev + jb);
         a.cand = reinterpret_cast<const uint32_t*>(B.dev + jb + fb);
+        a.spheres = reinterpret_cast<const float4*>(B.dev + sb);
         a.n_jobs = (uint32_t)plan.size();
         a.n_frames = frames;
         a.n_cand_total = cands;
@@ -1035,6 +1072,30 @@ int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_ra
     HIP_TRY(hipSetDevice(ctx->device));
     const hipError_t e = svo::launch_primary_rays(c, out_rays, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SVO_EDEVICE, "ray generation launch failed: %s", hipGetErrorString(e));
+    return SVO_OK;
+}
+
+int svo_generate_ao_rays(svo_ctx* ctx, const float* rays, const float* t, const float* normal, uint64_t n, uint32_t k,
+                         uint32_t seed, float radius, float offset, float* out_rays, void* stream) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    if (n == 0 || k == 0) return SVO_OK;
+    if (!rays || !t || !normal || !out_rays) return fail(SVO_EINVAL, "rays, t, normal and out_rays are required");
+    if ((((uintptr_t)rays) | ((uintptr_t)out_rays)) & 15u) return fail(SVO_EINVAL, "ray buffers must be 16-byte aligned");
+    if (n * (uint64_t)k > 0xFF000000ull) return fail(SVO_ERANGE, "too many rays");
+    if (!(radius >= 0.f) || !std::isfinite(offset)) return fail(SVO_EINVAL, "bad radius or offset");
+    svo::AoArgs a{};
+    a.rays = reinterpret_cast<const float4*>(rays);
+    a.t = t;
+    a.normal = normal;
+    a.n = n;
+    a.k = k;
+    a.seed = seed;
+    a.radius = radius;
+    a.offset = offset;
+    a.out = reinterpret_cast<float4*>(out_rays);
+    HIP_TRY(hipSetDevice(ctx->device));
+    const hipError_t e = svo::launch_ao_rays(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SVO_EDEVICE, "AO ray launch failed: %s", hipGetErrorString(e));
     return SVO_OK;
 }
 

@@ -59,6 +59,7 @@ struct TraceArgs {
     JobRec job0;
     const FrameRec* frames;   // n_frames records; job j's slot s is frames[frame_base_j + 1 + s]
     const uint32_t* cand;     // candidate frames (absolute indices), per job contiguous
+    const float4* spheres;    // n_frames world bounding spheres (centre, radius) of the moved root cells
     uint32_t n_jobs;
     uint32_t n_frames;
     uint32_t n_cand_total;
@@ -90,6 +91,21 @@ struct CameraArgs {
 };
 
 hipError_t launch_primary_rays(const CameraArgs& c, float* out, hipStream_t stream);
+
+// Ambient-occlusion rays from primary hits (see svo_raygen.hip).
+struct AoArgs {
+    const float4* rays;       // primary rays, 2 x float4 each
+    const float* t;           // primary hit t (+inf: miss)
+    const float* normal;      // 3 floats per primary ray
+    uint64_t n;
+    uint32_t k;               // AO rays per primary ray
+    uint32_t seed;
+    float radius;             // AO ray tmax
+    float offset;             // origin lift along the normal, relative to max(1, |p|inf)
+    float4* out;              // n * k rays
+};
+
+hipError_t launch_ao_rays(const AoArgs& a, hipStream_t stream);
 
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block);
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream);

@@ -93,6 +93,25 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
     return te <= fminf(tx, tlimit);
 }
 
+// Bounding-sphere test of the paper's Sec. 4.1 (Eq. 4), made conservative
+// for FP32: false only when the ray segment [tmin, tlimit] certainly misses
+// the sphere (its perpendicular distance exceeds the radius, or the sphere
+// lies wholly before tmin or after tlimit).  The radius is inflated by a
+// relative 1e-4 plus 1e-6 of the centre distance to absorb rounding.
+__device__ __forceinline__ bool sphere_may_hit(const float4 sp, const Ray& r, float tlimit) {
+    const float lx = sp.x - r.ox, ly = sp.y - r.oy, lz = sp.z - r.oz;
+    const float dd = fmaf(r.dx, r.dx, fmaf(r.dy, r.dy, r.dz * r.dz));
+    const float ll = fmaf(lx, lx, fmaf(ly, ly, lz * lz));
+    const float tca = fmaf(lx, r.dx, fmaf(ly, r.dy, lz * r.dz));
+    const float rr = sp.w * 1.0001f;
+    const float r2 = fmaf(rr, rr, 1e-6f * ll);
+    const float perp2 = ll - tca * tca / dd;            // squared distance of the line from the centre
+    if (perp2 > r2) return false;
+    const float half = sqrtf(fmaxf(r2 - perp2, 0.f) / dd);  // half chord, in t
+    const float tc = tca / dd;                            // t of the closest approach
+    return (tc - half <= tlimit) && (tc + half >= r.tmin);
+}
+
 __device__ __forceinline__ bool ray_valid(const Ray& r) {
     const bool fin = isfinite(r.ox) && isfinite(r.oy) && isfinite(r.oz) && isfinite(r.dx) && isfinite(r.dy) &&
                      isfinite(r.dz);
@@ -119,7 +138,7 @@ __device__ __forceinline__ void gst(T* p, uint64_t i, T v) {
 }  // namespace
 
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
-    const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 64 +
+    const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 80 +
                           align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec);
     const size_t per_wave = (a.sort_cand ? (size_t)a.max_cand * 64 * 4 : 0) + (size_t)a.stack_levels * 64 * 8 +
                             (size_t)a.nest_levels * 64 * 16;
@@ -133,6 +152,8 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     p += align16((size_t)a.lds_nodes * 8);
     FrameRec* lds_frames = reinterpret_cast<FrameRec*>(p);
     p += (size_t)a.n_frames * 64;
+    float4* lds_sph = reinterpret_cast<float4*>(p);
+    p += (size_t)a.n_frames * 16;
     uint32_t* lds_cand = reinterpret_cast<uint32_t*>(p);
     p += align16((size_t)a.n_cand_total * 4);
     JobRec* lds_jobs = reinterpret_cast<JobRec*>(p);
@@ -152,6 +173,7 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
         uint4* dst = reinterpret_cast<uint4*>(lds_frames);
         for (uint32_t i = threadIdx.x; i < a.n_frames * 4u; i += blockDim.x) dst[i] = src[i];
     }
+    for (uint32_t i = threadIdx.x; i < a.n_frames; i += blockDim.x) lds_sph[i] = a.spheres[i];
     for (uint32_t i = threadIdx.x; i < a.n_cand_total; i += blockDim.x) lds_cand[i] = a.cand[i];
     if (a.jobs) {
         const uint4* src = reinterpret_cast<const uint4*>(a.jobs);
@@ -295,11 +317,15 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                         tl = r.tmax;
                         if (a.sort_cand) {
                             for (uint32_t c = 0; c < ncand; ++c) {
-                                FrameRay cfr;
-                                float t0;
-                                int ea;
-                                const bool in = frame_setup(lds_frames[lds_cand[cbase + c]], r, tl, cfr, t0, ea);
-                                ent[c * 64] = in ? t0 : INFINITY;
+                                const uint32_t f = lds_cand[cbase + c];
+                                float e = INFINITY;
+                                if (sphere_may_hit(lds_sph[f], r, tl)) {
+                                    FrameRay cfr;
+                                    float t0;
+                                    int ea;
+                                    if (frame_setup(lds_frames[f], r, tl, cfr, t0, ea)) e = t0;
+                                }
+                                ent[c * 64] = e;
                             }
                         }
                         mode = start_frame(fbase) ? M_WALK : M_SELECT;
@@ -484,11 +510,17 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                     if (start_frame(lds_cand[cbase + pick])) mode = M_WALK;
                 }
             } else {
-                if (cnext >= ncand) {
-                    finish();
-                } else {
+                // candidates in index order; the sphere test (Sec. 4.1) rejects
+                // most before the exact setup
+                bool started = false;
+                while (cnext < ncand && !started) {
                     const uint32_t f = lds_cand[cbase + cnext++];
-                    if (start_frame(f)) mode = M_WALK;
+                    if (sphere_may_hit(lds_sph[f], r, tl)) started = start_frame(f);
+                }
+                if (started) {
+                    mode = M_WALK;
+                } else if (cnext >= ncand) {
+                    finish();
                 }
             }
         }

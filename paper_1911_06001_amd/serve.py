@@ -81,6 +81,7 @@ class _Active:
     fwd: np.ndarray
     next_ray: int = 0        # first ray not yet submitted
     pending_chunks: int = 0  # submitted chunks not yet complete
+    frames: int = 1          # frame records one chunk of this request takes
 
 
 class Scheduler:
@@ -88,12 +89,25 @@ class Scheduler:
 
     admit(): move waiting requests (first come, first served) into the
     active set while their footprint fits the budget.  plan(): pick the next
-    step's chunks, up to `max_rays` rays, oldest admitted request first.
+    step's chunks, at most `max_rays` rays, `max_jobs` chunks and `max_frames`
+    frame records (a launch's limits), oldest admitted request first:
+      fifo  each request takes what is left of the step's rays in turn;
+      fair  the step's rays are shared evenly among the requests with work
+            left (at least `min_chunk` each), so a small request admitted
+            behind a large one finishes in the next step instead of waiting
+            for the large one to drain.
     """
 
-    def __init__(self, budget: int, max_rays: int):
+    def __init__(self, budget: int, max_rays: int, policy: str = "fair", min_chunk: int = 1 << 16,
+                 max_jobs: int = 256, max_frames: int = 2047):
+        if policy not in ("fifo", "fair"):
+            raise ValueError(policy)
         self.budget = int(budget)
         self.max_rays = int(max_rays)
+        self.policy = policy
+        self.min_chunk = int(min_chunk)
+        self.max_jobs = int(max_jobs)
+        self.max_frames = int(max_frames)
         self.used = 0
         self.max_used = 0
 
@@ -113,19 +127,21 @@ class Scheduler:
         self.used -= req.footprint
 
     def plan(self, active: list) -> list:
-        """[(active, lo, hi)] covering at most max_rays rays; advances next_ray."""
-        chunks, left = [], self.max_rays
-        for a in active:
-            if left <= 0:
+        """[(active, lo, hi)] within the step limits; advances next_ray."""
+        work = [a for a in active if a.req.rays > a.next_ray]
+        chunks, left, frames = [], self.max_rays, 0
+        share = left
+        if self.policy == "fair" and work:
+            share = max(self.min_chunk, left // min(len(work), self.max_jobs))
+        for a in work:
+            if left <= 0 or len(chunks) >= self.max_jobs or frames + a.frames > self.max_frames:
                 break
-            todo = a.req.rays - a.next_ray
-            if todo <= 0:
-                continue
-            k = min(todo, left)
+            k = min(a.req.rays - a.next_ray, share, left)
             chunks.append((a, a.next_ray, a.next_ray + k))
             a.next_ray += k
             a.pending_chunks += 1
             left -= k
+            frames += a.frames
         return chunks
 
 
@@ -147,7 +163,8 @@ def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: 
 
 class Server:
     def __init__(self, ctx: svo.Context, scenes: Dict[str, SceneEntry], hbm_budget: int,
-                 max_rays_per_step: int = 1 << 22, inflight_steps: int = 2, keep_outputs: bool = False):
+                 max_rays_per_step: int = 1 << 22, inflight_steps: int = 2, keep_outputs: bool = False,
+                 policy: str = "fair"):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -156,8 +173,10 @@ class Server:
         self.max_rays = int(max_rays_per_step)
         self.inflight_steps = int(inflight_steps)
         self.keep = keep_outputs
+        self.policy = policy
         self.stream = torch.cuda.current_stream()
         self.dev = torch.device("cuda:%d" % ctx.device)
+        self.frames = {k: 1 + ctx.scene_stats(e.handle).n_slots for k, e in scenes.items()}
 
     # -- helpers
     def _camera(self, req: Request):
@@ -186,7 +205,7 @@ class Server:
         active: List[_Active] = []
         inflight = collections.deque()   # (event, [(active, n_rays)])
         results: List[Result] = []
-        sched = Scheduler(self.budget, self.max_rays)
+        sched = Scheduler(self.budget, self.max_rays, self.policy)
         self.scheduler = sched
         t.cuda.synchronize()
         start_ev = t.cuda.Event(enable_timing=True)
@@ -197,7 +216,8 @@ class Server:
             entry = self.scenes[req.scene]
             rays = self.ctx.primary_rays(self._camera(req), stream=self.stream)
             res = Result(req, admitted=time.perf_counter() - t0)
-            a = _Active(req, res, rays, self._buffers(req.rays), np.ascontiguousarray(entry.xform(req.frame), np.float32))
+            a = _Active(req, res, rays, self._buffers(req.rays), np.ascontiguousarray(entry.xform(req.frame), np.float32),
+                        frames=self.frames[req.scene])
             active.append(a)
             return a
 

@@ -27,7 +27,8 @@ MAX_INLINE_NEST = 4
 # every symbol include/svo.h declares
 EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
-           "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays")
+           "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
+           "svo_generate_ao_rays")
 
 
 class SvoError(RuntimeError):
@@ -116,6 +117,7 @@ def lib():
         "svo_trace_batch": (I, [P, ctypes.POINTER(Job), U32, P]),
         "svo_tune": (I, [P, U32, P, U64, P, ctypes.POINTER(Config)]),
         "svo_generate_primary_rays": (I, [P, ctypes.POINTER(Camera), P, P]),
+        "svo_generate_ao_rays": (I, [P, P, P, P, U64, U32, U32, ctypes.c_float, ctypes.c_float, P, P]),
         "svo_get_config": (I, [P, ctypes.POINTER(Config)]),
         "svo_set_config": (I, [P, ctypes.POINTER(Config)]),
     }
@@ -264,6 +266,18 @@ class Context:
         if out.shape[0] < n:
             raise ValueError("output buffer too small")
         _check(lib().svo_generate_primary_rays(self._ptr, ctypes.byref(cam), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def ao_rays(self, rays, hits: "Hits", k: int, seed: int, radius: float, offset: float = 1e-3, out=None,
+                stream=None):
+        """k cosine-weighted AO rays per primary ray, as a device tensor [n * k, 8]."""
+        import torch
+        n = rays.shape[0]
+        if out is None:
+            out = torch.empty((n * k, 8), dtype=torch.float32, device=rays.device)
+        _check(lib().svo_generate_ao_rays(self._ptr, rays.data_ptr(), hits.t.data_ptr(), hits.normal.data_ptr(), n, int(k),
+                                          int(seed) & 0xFFFFFFFF, float(radius), float(offset), out.data_ptr(),
+                                          _stream_handle(stream)))
         return out
 
     def trace_batch(self, jobs, stream=None):

@@ -74,3 +74,34 @@ def fbm3(x, y, z, octaves: int, period0: float, seed: int):
         total = total + amp * value_noise3(x, y, z, period0 / 2.0 ** o, o, seed)
         amp_sum += amp
     return total / amp_sum
+
+
+def value_noise3_grid(n: int, period: float, octave: int, seed: int, dtype=np.float32):
+    """value_noise3 at every voxel centre (i + 1/2) of an n^3 grid, computed by
+    separable interpolation: the lattice values are hashed once, then blended
+    along x, y and z in turn (the same smoothstep weights as value_noise3)."""
+    g = (np.arange(n, dtype=np.float64) + 0.5) / period
+    i0 = np.floor(g).astype(np.int64)
+    w = _smooth(g - i0)
+    lo, hi = int(i0.min()), int(i0.max()) + 1
+    L = np.arange(lo, hi + 1, dtype=np.int64)
+    V = to_signed_unit(hash_keys(L[:, None, None], L[None, :, None], L[None, None, :], octave, seed, 3))
+    ix = i0 - lo
+    # blend along x: [n, Ly, Lz]
+    A = V[ix] * (1 - w)[:, None, None] + V[ix + 1] * w[:, None, None]
+    # along y: [n, n, Lz]
+    B = A[:, ix, :] * (1 - w)[None, :, None] + A[:, ix + 1, :] * w[None, :, None]
+    B = B.astype(dtype)
+    wz = w.astype(dtype)
+    return B[:, :, ix] * (1 - wz)[None, None, :] + B[:, :, ix + 1] * wz[None, None, :]
+
+
+def fbm3_grid(n: int, octaves: int, period0: float, seed: int, dtype=np.float32):
+    total = np.zeros((n, n, n), dtype=dtype)
+    amp_sum = 0.0
+    for o in range(octaves):
+        amp = 2.0 ** -o
+        total += dtype(amp) * value_noise3_grid(n, period0 / 2.0 ** o, o, seed, dtype)
+        amp_sum += amp
+    total /= dtype(amp_sum)
+    return total

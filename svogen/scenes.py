@@ -323,3 +323,122 @@ def blob_occupancy(K: int, seed: int, density: float = 0.4) -> np.ndarray:
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
     v = fbm3(X, Y, Z, 2, max(2.0, n / 2.0), seed)
     return v > (1.0 - 2.0 * density) * 0.5
+
+
+# ------------------------------------------------------------------ instanced scene, 4096^3 world
+
+def _instance_trees(seed: int):
+    """The four instance SVOs: sphere (depth 8, radius 96), noise blob (depth
+    9: 4-octave value noise > 0.1 inside radius 240), heightfield (depth 10)
+    and box lattice (depth 11: solid where at least two of x, y, z mod 128
+    fall below 16)."""
+    trees = []
+    # sphere
+    K = 8
+    n = 1 << K
+    g = np.arange(n, dtype=np.float32) + 0.5
+    r2 = (g[:, None, None] - n / 2) ** 2 + (g[None, :, None] - n / 2) ** 2 + (g[None, None, :] - n / 2) ** 2
+    occ = r2 < 96.0 ** 2
+    trees.append(ot.build_tree(K, ot.dense_classifier(occ)[0], _colour_fn(K, seed)))
+    del occ, r2
+    # noise blob
+    K = 9
+    n = 1 << K
+    from .noise import fbm3_grid
+    occ = fbm3_grid(n, 4, 128.0, seed) > 0.1
+    g = np.arange(n, dtype=np.float32) + 0.5
+    occ &= ((g[:, None, None] - n / 2) ** 2 + (g[None, :, None] - n / 2) ** 2 + (g[None, None, :] - n / 2) ** 2) < 240.0 ** 2
+    trees.append(ot.build_tree(K, ot.dense_classifier(occ)[0], _colour_fn(K, seed)))
+    del occ
+    # heightfield
+    K = 10
+    H = heightfield(K, seed, 400.0, 300.0, 6, 256.0)
+    trees.append(ot.build_tree(K, ot.heightfield_classifier(H, K), _colour_fn(K, seed)))
+    # box lattice
+    K = 11
+    trees.append(ot.build_tree(K, ot.lattice_classifier(K, 128, 16), _colour_fn(K, seed)))
+    return trees
+
+
+def instanced_scene(seed: int = 3, n_inst: int = 64, world_K: int = 12) -> Scene:
+    """64 instances of the four SVOs in a 4096^3 world.  Instance i has kind
+    i mod 4, sits on a free cell at a level drawn from {1, 2, 3} (no used
+    cell above or below it), and maps its own root cube [0, 2^D)^3 onto the
+    cell (placement), then rotates uniformly at random, scales each axis by
+    U[0.5, 1] about the cell centre and moves by U[-1/4, 1/4] cell (pose).
+    Instances of one kind share their subtree (slots share a child group)."""
+    st = Stream(seed, 51)
+    inst = _instance_trees(seed)
+    N = 1 << world_K
+    used = []
+    cells = []
+    tries = 0
+    while len(cells) < n_inst and tries < 100000:
+        tries += 1
+        L = int(st.integers(1, 1, 4)[0])
+        xyz = tuple(int(v) for v in st.integers(3, 0, 1 << L))
+        ok = True
+        for (l2, c2) in used:
+            lo, hi = (l2, L) if l2 < L else (L, l2)
+            a, b = (c2, xyz) if l2 < L else (xyz, c2)
+            if lo == hi:
+                if a == b:
+                    ok = False
+                    break
+            elif all((b[k] >> (hi - lo)) == a[k] for k in range(3)):
+                ok = False
+                break
+        if ok:
+            used.append((L, xyz))
+            cells.append((L, xyz))
+    if len(cells) < n_inst:
+        raise RuntimeError("could not place all instances")
+    grafts = {}
+    for s, (L, xyz) in enumerate(cells):
+        grafts[(L,) + xyz] = (s, inst[s % 4].root_mask)
+    graft_set = {(L,) + xyz for (L, xyz) in cells}
+
+    def classify(l, c):
+        out = np.zeros(c.shape[0], np.uint8)
+        for j in range(c.shape[0]):
+            cj = tuple(int(v) for v in c[j])
+            for (L, xyz) in cells:
+                if L > l and all((xyz[k] >> (L - l)) == cj[k] for k in range(3)):
+                    out[j] = ot.PARTIAL
+                    break
+        return out
+
+    world = ot.build_tree(world_K, classify, None, grafts=grafts)
+    nodes, bases = ot.concat([world] + inst)
+    slot_child = np.array([bases[1 + s % 4] + int(inst[s % 4].child_start[0]) for s in range(n_inst)], np.uint32)
+    slot_cell = np.array([[0.0, 0.0, 0.0, float(1 << inst[s % 4].K)] for s in range(n_inst)], np.float32)
+    slot_node = np.array([ot.find_node(world, L, xyz) for (L, xyz) in cells], np.int64)
+    mats = []
+    for s, (L, xyz) in enumerate(cells):
+        size = float(N >> L)
+        lo = np.asarray(xyz, np.float64) * size
+        D = inst[s % 4].K
+        place = np.zeros((3, 4))
+        place[:, :3] = np.eye(3) * (size / float(1 << D))
+        place[:, 3] = lo
+        R = xf.random_rotation(st)
+        sc = st.uniform(3, 0.5, 1.0)
+        tr = st.uniform(3, -0.25, 0.25) * size
+        pose = xf.about_pivot(R @ np.diag(sc), lo + size / 2, tr)
+        A = pose[:, :3] @ place[:, :3]
+        b = pose[:, :3] @ place[:, 3] + pose[:, 3]
+        M = np.zeros((3, 4))
+        M[:, :3] = A
+        M[:, 3] = b
+        mats.append(xf.to_f32(M).reshape(12))
+    F = np.array(mats, np.float32)
+
+    def xform(frame: int = 0):
+        return F.copy()
+
+    static = ot.clear_transformed(nodes, slot_child)
+    camera = dict(eye=(2048.0, 3000.0, -2500.0), target=(2048.0, 1800.0, 2048.0), up=(0.0, 1.0, 0.0), fov=60.0,
+                  W=1920, H=1080)
+    return Scene(name="instances4096", nodes=nodes, static_nodes=static, root=0, root_min=np.zeros(3, np.float32),
+                 root_size=float(N), max_depth=20, slot_child=slot_child, slot_cell=slot_cell, slot_node=slot_node,
+                 slot_parent=np.full(n_inst, NONE, np.uint32), tree=world, xform=xform, camera=camera, seed=seed)

@@ -10,17 +10,17 @@ import pytest
 from paper_1911_06001_amd.serve import Request, Scheduler, _Active, Result, poisson_requests
 
 
-def _sim(reqs, budget, max_rays, finish_after=2, seed=0):
+def _sim(reqs, budget, max_rays, finish_after=2, seed=0, policy="fair", max_jobs=256):
     """Drive the scheduler with a fake executor: a step completes
     `finish_after` plans after it was issued."""
     rng = np.random.default_rng(seed)
-    s = Scheduler(budget, max_rays)
+    s = Scheduler(budget, max_rays, policy=policy, min_chunk=16, max_jobs=max_jobs, max_frames=40)
     waiting = collections.deque(reqs)
     active, inflight, order, done = [], collections.deque(), [], []
     covered = {r.rid: np.zeros(r.rays, np.int32) for r in reqs}
     while waiting or active or inflight:
         def on_admit(req):
-            a = _Active(req, Result(req), None, {}, None)
+            a = _Active(req, Result(req), None, {}, None, frames=9 if req.scene == "b" else 2)
             active.append(a)
             order.append(req.rid)
             return a
@@ -31,6 +31,7 @@ def _sim(reqs, budget, max_rays, finish_after=2, seed=0):
             assert hi - lo > 0
             covered[a.req.rid][lo:hi] += 1
         assert sum(hi - lo for _, lo, hi in chunks) <= max_rays
+        assert len(chunks) <= max_jobs and sum(a.frames for a, _, _ in chunks) <= 40
         if chunks:
             inflight.append(chunks)
         if inflight and (len(inflight) >= finish_after or not chunks or rng.random() < 0.3):
@@ -43,10 +44,11 @@ def _sim(reqs, budget, max_rays, finish_after=2, seed=0):
     return s, order, done, covered
 
 
-def test_budget_fifo_and_exact_coverage():
+@pytest.mark.parametrize("policy", ["fifo", "fair"])
+def test_budget_fifo_and_exact_coverage(policy):
     reqs = poisson_requests(60, 1000.0, 4, ["a", "b"], resolutions=((16, 16), (40, 30), (64, 48)), samples=(1, 3))
     budget = max(r.footprint for r in reqs) * 3
-    s, order, done, covered = _sim(reqs, budget, max_rays=5000)
+    s, order, done, covered = _sim(reqs, budget, max_rays=5000, policy=policy, max_jobs=5)
     assert order == sorted(order)                      # admitted first come first served
     assert sorted(done) == [r.rid for r in reqs]      # everything finished
     assert all((c == 1).all() for c in covered.values())   # each ray submitted exactly once
@@ -72,3 +74,15 @@ def test_poisson_trace_is_seeded():
     assert [(r.arrival, r.scene, r.width, r.samples) for r in a] == [(r.arrival, r.scene, r.width, r.samples) for r in b]
     gaps = np.diff([r.arrival for r in a])
     assert (gaps >= 0).all() and 0.003 < gaps.mean() < 0.03
+
+
+def test_fair_share_lets_small_requests_through():
+    big = Request(0, 0.0, "a", 0, 1000, 1000, 1)
+    small = Request(1, 0.0, "a", 0, 8, 8, 1)
+    for policy, small_first_step in (("fifo", False), ("fair", True)):
+        s = Scheduler(10**12, max_rays=100000, policy=policy, min_chunk=64)
+        active = []
+        s.admit(collections.deque([big, small]), lambda r: active.append(_Active(r, Result(r), None, {}, None)) or active[-1])
+        chunks = s.plan(active)
+        got_small = any(a.req.rid == 1 for a, _, _ in chunks)
+        assert got_small == small_first_step, policy
