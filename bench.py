@@ -68,6 +68,8 @@ def cpu_baseline(scene, rays, frames, budget_s):
     spent = 0.0
     bytes_sum = 0.0
     frame_list = []
+    nnode = []
+    nframe = []
     f = 0
     while spent < budget_s and f < frames:
         t0 = time.perf_counter()
@@ -77,9 +79,24 @@ def cpu_baseline(scene, rays, frames, budget_s):
         # algorithmic bytes per ray: 8 B per node record, 64 B per frame
         # record, 32 B ray in, 24 B hit out
         bytes_sum += float((8.0 * h.nnode.astype(np.float64) + 64.0 * h.nframe + 32.0 + 24.0).sum())
+        nnode.append(h.nnode)
+        nframe.append(h.nframe)
         frame_list.append(f)
         f += 1
-    return dict(rays=done, seconds=spent, threads=threads, frames=frame_list, bytes_per_ray=bytes_sum / max(done, 1))
+    nn = np.concatenate(nnode) if nnode else np.zeros(1)
+    nf = np.concatenate(nframe) if nframe else np.zeros(1)
+    return dict(rays=done, seconds=spent, threads=threads, frames=frame_list, bytes_per_ray=bytes_sum / max(done, 1),
+                n_node_mean=float(nn.mean()), n_node_p99=float(np.percentile(nn, 99)), n_frame_mean=float(nf.mean()))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def instances_throughput(ctx, steps):
@@ -124,11 +141,14 @@ def instances_throughput(ctx, steps):
     return res
 
 
-def serve_latency(ctx, terrain, terrain_handle, n_requests, load):
-    """p50/p99 frame latency of a Poisson request stream over the noisy-sphere
-    and terrain scenes (resolutions 256^2 .. 2048x1152, 1-5 rays per pixel),
-    continuously batched vs one request per launch, at `load` x the batched
-    saturation rate, under a 16 GiB device-memory budget."""
+def serve_latency(ctx, terrain, terrain_handle, n_requests, loads, warm=100):
+    """p50/p99 frame latency of Poisson request streams over the noisy-sphere
+    and terrain scenes (resolutions 256^2 .. 2048x1152, 1-5 rays per pixel)
+    at each offered load (a fraction of the batched saturation rate), under a
+    16 GiB device-memory budget: continuously batched with the launch
+    replayed from a captured HIP graph, continuously batched with eager
+    launches, and one request per launch.  The first `warm` requests of each
+    stream are excluded from the statistics."""
     from paper_1911_06001_amd import serve
     from svogen import scenes
     sph = scenes.noisy_sphere_d6()
@@ -136,23 +156,33 @@ def serve_latency(ctx, terrain, terrain_handle, n_requests, load):
     entries = {"sphere": serve.SceneEntry(hs, sph.xform, sph.camera),
                "terrain": serve.SceneEntry(terrain_handle, terrain.xform, terrain.camera)}
     budget = 16 << 30
+    warm = min(warm, n_requests // 5)
     srv = serve.Server(ctx, entries, hbm_budget=budget)
+    srv_g = serve.Server(ctx, entries, hbm_budget=budget, graph=True)
     names = ["sphere", "terrain"]
-    warm = serve.poisson_requests(20, 1e9, 40, names)
-    srv.run(warm, "batched")
+    srv_g.run(serve.poisson_requests(20, 1e9, 40, names), "batched")
+    srv.run(serve.poisson_requests(20, 1e9, 40, names), "batched")
     burst = serve.poisson_requests(max(40, n_requests // 3), 1e9, 41, names)
-    sat = serve.summarize(srv.run(burst, "batched"))
+    sat = serve.summarize(srv_g.run(burst, "batched"))
     rate = sat["requests"] / sat["makespan_s"]
-    trace = serve.poisson_requests(n_requests, load * rate, 42, names)
-    b = serve.summarize(srv.run(trace, "batched"))
-    s1 = serve.summarize(srv.run(trace, "single"))
+    points = []
+    for i, load in enumerate(loads):
+        trace = serve.poisson_requests(n_requests, load * rate, 42 + i, names)
+        keep = lambda res: [r for r in res if r.req.rid >= warm]
+        pt = {"offered_load": load, "rate_rps": round(load * rate, 1),
+              "batched_graph": serve.summarize(keep(srv_g.run(trace, "batched"))),
+              "batched": serve.summarize(keep(srv.run(trace, "batched"))),
+              "single": serve.summarize(keep(srv.run(trace, "single")))}
+        log("serving load %.1f: graph p50 %.2f p99 %.2f | eager p50 %.2f p99 %.2f | single p50 %.2f p99 %.2f ms" % (
+            load, pt["batched_graph"]["p50_ms"], pt["batched_graph"]["p99_ms"], pt["batched"]["p50_ms"],
+            pt["batched"]["p99_ms"], pt["single"]["p50_ms"], pt["single"]["p99_ms"]))
+        points.append(pt)
+    srv_g.close()
     ctx.free_scene(hs)
-    log("serving: saturation %.0f req/s; batched p50 %.2f p99 %.2f ms; single p50 %.2f p99 %.2f ms" %
-        (rate, b["p50_ms"], b["p99_ms"], s1["p50_ms"], s1["p99_ms"]))
-    return {"requests": n_requests, "offered_load": load, "saturation_rps": round(rate, 1),
-            "rate_rps": round(load * rate, 1), "hbm_budget_bytes": budget,
+    return {"requests": n_requests, "warmup_requests": warm, "saturation_rps": round(rate, 1),
+            "hbm_budget_bytes": budget, "policy": srv.policy, "max_rays_per_step": srv.max_rays,
             "mix": "sphere64 + terrain1024 scenes, 256^2/720p/1080p/2048x1152, 1-5 rays per pixel, Poisson arrivals",
-            "batched": b, "single": s1}
+            "points": points}
 
 
 def main():
@@ -168,11 +198,12 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-cache-nodes", type=int, default=-1)
     ap.add_argument("--refill", type=int, default=-1)
-    ap.add_argument("--serve-requests", type=int, default=300,
-                    help="requests in the served-latency run (0 disables)")
-    ap.add_argument("--serve-load", type=float, default=0.6, help="offered load as a fraction of saturation")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests per offered load in the served-latency runs (0 disables)")
+    ap.add_argument("--serve-loads", default="0.3,0.6,0.9", help="offered loads, fractions of saturation")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--no-instances", action="store_true", help="skip the instanced-scene measurement")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the gather / stream ceiling kernels")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -283,7 +314,7 @@ def main():
         cb = cpu_baseline(sc, rays_np, args.frames, args.cpu_seconds)
         bytes_per_ray = cb["bytes_per_ray"]
         cpu = {"value": round(cb["rays"] / cb["seconds"] / 1e6, 4), "unit": "Mrays/s", "cores": cb["threads"],
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                "sample": "animated terrain1024 frames %d..%d, all %d rays each (%d rays, %.1f s)" % (
                    cb["frames"][0], cb["frames"][-1], n, cb["rays"], cb["seconds"])}
     roof = None
@@ -293,14 +324,27 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "bytes_per_ray": round(bytes_per_ray, 2), "rays_per_launch": n,
-                "kernel_ms": round(kmean_a * 1e3, 4)}
+                "kernel_ms": round(kmean_a * 1e3, 4),
+                "n_node_mean": round(cb["n_node_mean"], 2), "n_node_p99": round(cb["n_node_p99"], 1),
+                "n_frame_mean": round(cb["n_frame_mean"], 3)}
+
+    ceilings = None
+    if not args.no_ceilings:
+        from paper_1911_06001_amd import ceiling
+        kc = tuned or cfg
+        n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+        ceilings = ceiling.measure(int(sc.nodes.nbytes), n_cu * kc["blocks_per_cu"], 64 * kc["waves_per_block"])
+        log("ceilings", ceilings)
+        if roof is not None:
+            for k in ("gather_independent_GBps", "gather_dependent_GBps", "stream_pool_GBps", "stream_hbm_GBps"):
+                ceilings["frac_" + k[:-5]] = round(roof["achieved"] / ceilings[k], 4)
 
     instances = None
     if not args.no_instances:
         instances = instances_throughput(ctx, max(5, K // 6))
     serving = None
     if args.serve_requests > 0:
-        serving = serve_latency(ctx, sc, anim, args.serve_requests, args.serve_load)
+        serving = serve_latency(ctx, sc, anim, args.serve_requests, [float(x) for x in args.serve_loads.split(",")])
 
     out = {
         "metric": METRIC,
@@ -325,6 +369,7 @@ def main():
         "animated_over_static_time": round(wall_a / wall_s, 4),
         "animated_over_static_kernel_time": round(float(np.mean(kms_a)) / float(np.mean(kms_s)), 4),
         "roofline": roof,
+        "ceilings": ceilings,
         "cpu_baseline": cpu,
         "serving": serving,
         "instances": instances,

@@ -116,7 +116,7 @@ typedef struct {
 /* Kernel configuration; svo_tune() picks one, svo_set_config() sets one.
    Zero fields select the library defaults. */
 typedef struct {
-    uint32_t waves_per_block;   /* 1..16 wavefronts (64 lanes) per work-group */
+    uint32_t waves_per_block;   /* 1..8 wavefronts (64 lanes) per work-group */
     uint32_t blocks_per_cu;     /* resident work-groups per compute unit for the persistent grid */
     uint32_t lds_cache_nodes;   /* first N pool nodes (the top levels, breadth-first) kept in LDS */
     uint32_t refill_lanes;      /* 0 or 64: a wave takes 64-ray tiles; 1..63: claim new rays once that many lanes are idle */
@@ -214,6 +214,63 @@ typedef struct {
    job table is packed on the host into pinned memory and copied on `stream`
    (a ring of four tables; a fifth call waits for the first to finish). */
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Launch plans: a batched launch whose kernel arguments are fixed when the
+ * plan is created, so that one svo_plan_launch can be captured into a HIP
+ * graph (hipStreamBeginCapture, torch.cuda.graph) and replayed for every
+ * later batch.  Rays of many requests and scenes then run in one persistent
+ * launch per replay (one pixel/ray, Fig. 5), with no per-step launch setup;
+ * the jobs of each replay come from the plan's pinned staging table as it is
+ * when the replay's copy executes.  Results are identical to svo_trace_batch
+ * with the same jobs.
+ */
+typedef struct svo_plan svo_plan;
+
+/* Capacity of a plan. */
+typedef struct {
+    uint32_t max_jobs;        /* 1..256 non-empty jobs per launch */
+    uint32_t max_frames;      /* 1..2047 frame records per launch; a job takes 1 + n_slots of its scene */
+    uint32_t reserved[2];     /* zero */
+} svo_plan_limits;
+
+/* Create a plan for jobs on the given scenes (host array of n_scenes >= 1
+   handles).  The scenes fix the plan's traversal-stack and frame-nesting
+   capacity (bounds that hold under any transforms), the LDS candidate table
+   and the pool whose prefix is cached in LDS (the first scene's).  The
+   kernel configuration is the first scene's tuned one if it has one, else
+   the context's.  Allocates a device table, pinned staging of the same
+   size and a private work queue (zeroed; synchronous).  Errors: SVO_EINVAL
+   (NULL argument, unknown scene, non-zero reserved field), SVO_ERANGE
+   (limits out of range, or the plan's LDS footprint exceeds the device's
+   even with no node cache), SVO_ENOMEM, SVO_EDEVICE.  *out is NULL on
+   failure. */
+int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, const svo_plan_limits* limits,
+                    svo_plan** out);
+
+/* Pack jobs (host array, as for svo_trace_batch) into the plan's staging
+   table, host only.  Every non-empty job's scene must be one of the plan's
+   scenes; jobs without transforms use their scene's current ones, read now.
+   Waits until the plan's last eager launch has copied the staging.  After a
+   launch captured into a graph the library cannot see replays: the caller
+   must not call this while a replay may still be copying (wait for an event
+   recorded after the replay).  n_jobs == 0 (or only empty jobs) makes the
+   next launch trace nothing.  Errors: SVO_EINVAL (bad job, foreign scene),
+   SVO_ERANGE (more jobs, frame records or rays than the plan holds). */
+int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_t n_jobs);
+
+/* Enqueue the plan's launch on `stream`: a copy of the whole staging table
+   to the device table, then the persistent trace kernel on the plan's own
+   work queue (the kernel resets it on exit).  Allocates nothing and does not
+   synchronise the host, so it may be captured; a captured copy reads the
+   staging at every replay.  Launches of one plan must not overlap (one
+   stream, or ordered streams).  Errors: SVO_EINVAL, SVO_EDEVICE. */
+int svo_plan_launch(svo_ctx* ctx, svo_plan* plan, void* stream);
+
+/* Wait for the plan's eager launches and free it.  Graphs holding a
+   captured launch of the plan must not be replayed afterwards.  NULL is a
+   no-op. */
+int svo_plan_destroy(svo_ctx* ctx, svo_plan* plan);
 
 /* Current kernel configuration of the context / replace it (validated).
    svo_set_config also drops every scene's tuned configuration. */

@@ -104,7 +104,7 @@ def trace(nodes, root, root_min, root_size, slot_child, slot_cell, fwd, rays, ma
 def trace_scene(scene, rays, frame=0, static=False, margin=False, counters=False, fwd=None, nthreads=0,
                 margin_eps=1e-6, fwd_f64=False) -> Hits:
     """Convenience wrapper over a generated scene (svogen.scenes.Scene)."""
-    nodes = scene.static_nodes if static else scene.nodes
+    nodes = scene.static_pool() if static else scene.nodes
     if fwd is None:
         fwd = scene.xform(frame) if scene.n_slots else np.zeros((0, 12), np.float32)
     return trace(nodes, scene.root, scene.root_min, scene.root_size, scene.slot_child, scene.slot_cell, fwd, rays,

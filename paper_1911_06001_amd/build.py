@@ -16,9 +16,13 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Wall", "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc"] + FLAGS + SOURCES + ["-o", tmp]
+CEILING_LIB = os.path.join(HERE, "libsvo_ceiling.so")
+CEILING_SOURCES = [os.path.join(HERE, "csrc", "svo_ceiling.hip")]
+
+
+def _hipcc(sources, out: str, verbose: bool):
+    tmp = out + ".tmp"
+    cmd = ["hipcc"] + FLAGS + sources + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -27,7 +31,14 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
     if verbose and errs:
         print("\n".join(errs))
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libsvo.so (the trace library) and libsvo_ceiling.so (memory
+    ceilings for its roofline)."""
+    _hipcc(SOURCES, LIB, verbose)
+    _hipcc(CEILING_SOURCES, CEILING_LIB, verbose)
     return LIB
 
 

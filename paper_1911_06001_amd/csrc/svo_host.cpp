@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -298,7 +299,7 @@ struct Scene {
     int cur = 0;                        // table the next trace reads
     uint32_t n_frames = 1;              // 1 + n_slots records per table
     // classification of the current table
-    uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0;
+    uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0, n_bvh = 0, bvh_depth = 0;
     uint64_t bytes = 0;
     bool tuned = false;                 // svo_tune picked `cfg` for this scene
     svo_config cfg{};
@@ -325,7 +326,39 @@ struct svo_ctx {
     };
     BatchBuf batch[4];
     uint32_t next_batch = 0;
+    std::set<svo_plan*> plans;
 };
+
+// A reusable launch (svo_plan_*): fixed kernel arguments over a device
+// table of fixed capacity, filled from pinned staging by each launch.
+struct svo_plan {
+    std::set<svo_scene> scenes;
+    svo_config cfg{};
+    svo::TraceArgs args{};
+    svo::LaunchCfg launch_cfg{};
+    uint32_t max_jobs = 0, max_frames = 0, max_cand = 0, stack_cap = 1, nest_cap = 0, max_bvh = 0, bvh_depth_cap = 0;
+    size_t off_jobs = 0, off_frames = 0, off_cand = 0, off_sph = 0, off_bvh = 0, bytes = 0;
+    unsigned char* dev = nullptr;
+    unsigned char* host = nullptr;
+    uint32_t* d_queue = nullptr;
+    hipEvent_t ev = nullptr;
+    bool ev_pending = false;   // an eager launch's copy of the staging may still run
+};
+
+namespace {
+
+void destroy_plan(svo_plan& p) {
+    if (p.dev) (void)hipFree(p.dev);
+    if (p.host) (void)hipHostFree(p.host);
+    if (p.d_queue) (void)hipFree(p.d_queue);
+    if (p.ev) (void)hipEventDestroy(p.ev);
+    p.dev = nullptr;
+    p.host = nullptr;
+    p.d_queue = nullptr;
+    p.ev = nullptr;
+}
+
+}  // namespace
 
 namespace {
 
@@ -368,13 +401,87 @@ inline size_t cand_offset(uint32_t n_frames) { return (size_t)n_frames * sizeof(
 inline size_t sphere_offset(uint32_t n_frames, uint32_t n_slots) {
     return (cand_offset(n_frames) + (size_t)n_slots * sizeof(uint32_t) + 15) & ~(size_t)15;
 }
-inline size_t table_size(uint32_t n_frames, uint32_t n_slots) {
+// ... then the hierarchy over the candidates (at most 2 n_slots nodes).
+inline size_t bvh_offset(uint32_t n_frames, uint32_t n_slots) {
     return sphere_offset(n_frames, n_slots) + (size_t)n_frames * 16;
+}
+inline uint32_t bvh_capacity(uint32_t n_slots) { return std::max<uint32_t>(1, 2 * n_slots); }
+inline size_t table_size(uint32_t n_frames, uint32_t n_slots) {
+    return bvh_offset(n_frames, n_slots) + (size_t)bvh_capacity(n_slots) * sizeof(svo::BvhNode);
 }
 
 struct TableInfo {
-    uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0;
+    uint32_t n_cand = 0, stack_levels = 1, nest_levels = 0, n_inline = 0, n_bvh = 0, bvh_depth = 0;
 };
+
+// Levels of the hierarchy bvh_build makes over n candidates (median splits,
+// leaves of at most kBvhLeafMax).
+uint32_t bvh_levels(uint32_t n) {
+    if (n <= svo::kBvhLeafMax) return n ? 1u : 0u;
+    return 1u + std::max(bvh_levels(n / 2), bvh_levels(n - n / 2));
+}
+
+struct BItem {
+    double lo[3], hi[3], c[3];
+    uint32_t frame;
+};
+
+float round_down_f32(double v) {
+    float f = (float)v;
+    return ((double)f > v) ? std::nextafter(f, -INFINITY) : f;
+}
+float round_up_f32(double v) {
+    float f = (float)v;
+    return ((double)f < v) ? std::nextafter(f, INFINITY) : f;
+}
+
+// Median-split hierarchy over items [begin, end), nodes in depth-first
+// order from out[n]; returns the node index.  Boxes are widened by 1e-5 of
+// their extent plus 1e-6 of their magnitude and rounded outward to FP32.
+uint32_t bvh_build(std::vector<BItem>& it, uint32_t begin, uint32_t end, uint32_t level, svo::BvhNode* out,
+                   uint32_t& n, uint32_t& depth) {
+    const uint32_t me = n++;
+    depth = std::max(depth, level);
+    double lo[3], hi[3], clo[3], chi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = clo[a] = INFINITY;
+        hi[a] = chi[a] = -INFINITY;
+    }
+    for (uint32_t i = begin; i < end; ++i)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], it[i].lo[a]);
+            hi[a] = std::max(hi[a], it[i].hi[a]);
+            clo[a] = std::min(clo[a], it[i].c[a]);
+            chi[a] = std::max(chi[a], it[i].c[a]);
+        }
+    double ext = 0.0, mag = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        ext = std::max(ext, hi[a] - lo[a]);
+        mag = std::max(mag, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+    }
+    const double pad = 1e-5 * ext + 1e-6 * mag;
+    svo::BvhNode& N = out[me];
+    for (int a = 0; a < 3; ++a) {
+        N.lo[a] = round_down_f32(lo[a] - pad);
+        N.hi[a] = round_up_f32(hi[a] + pad);
+    }
+    if (end - begin <= svo::kBvhLeafMax) {
+        N.a = begin;
+        N.b = svo::kBvhLeaf | (end - begin);
+        return me;
+    }
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+        if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+    const uint32_t mid = begin + (end - begin) / 2;
+    std::nth_element(it.begin() + begin, it.begin() + mid, it.begin() + end,
+                     [axis](const BItem& x, const BItem& y) { return x.c[axis] < y.c[axis]; });
+    const uint32_t L = bvh_build(it, begin, mid, level + 1, out, n, depth);
+    const uint32_t R = bvh_build(it, mid, end, level + 1, out, n, depth);
+    out[me].a = L;
+    out[me].b = R;
+    return me;
+}
 
 // Compose, invert and pack the frame table into `out` (host): record 0 is
 // the world, record 1 + s slot s; the candidate list follows the records.
@@ -488,6 +595,38 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
         }
     }
     if (T.stack_levels > 127) return fail(SVO_ERANGE, "nested frames need %u stack levels (limit 127)", T.stack_levels);
+    // hierarchy over the candidates' world boxes (the image of each moved
+    // root cell), leaves in candidate-list order
+    if (T.n_cand) {
+        std::vector<BItem> items(T.n_cand);
+        for (uint32_t i = 0; i < T.n_cand; ++i) {
+            const uint32_t s = cand[i] - 1;
+            const float* cell = &S.slot_cell[4 * s];
+            BItem& b = items[i];
+            b.frame = cand[i];
+            for (int r = 0; r < 3; ++r) {
+                b.lo[r] = INFINITY;
+                b.hi[r] = -INFINITY;
+            }
+            for (int k = 0; k < 8; ++k) {
+                double x[3];
+                for (int a = 0; a < 3; ++a) x[a] = cell[a] + (((k >> a) & 1) ? cell[3] : 0.0);
+                for (int r = 0; r < 3; ++r) {
+                    const double v = world[s].m[r][0] * x[0] + world[s].m[r][1] * x[1] + world[s].m[r][2] * x[2] +
+                                     world[s].m[r][3];
+                    b.lo[r] = std::min(b.lo[r], v);
+                    b.hi[r] = std::max(b.hi[r], v);
+                }
+            }
+            for (int r = 0; r < 3; ++r) b.c[r] = 0.5 * (b.lo[r] + b.hi[r]);
+        }
+        svo::BvhNode* bn = reinterpret_cast<svo::BvhNode*>(out + bvh_offset(S.n_frames, S.n_slots));
+        uint32_t n = 0, depth = 0;
+        bvh_build(items, 0, T.n_cand, 1, bn, n, depth);
+        for (uint32_t i = 0; i < T.n_cand; ++i) cand[i] = items[i].frame;
+        T.n_bvh = n;
+        T.bvh_depth = depth;
+    }
     return SVO_OK;
 }
 
@@ -505,6 +644,8 @@ int upload_frames(Scene& S, hipStream_t stream) {
     S.stack_levels = T.stack_levels;
     S.nest_levels = T.nest_levels;
     S.n_inline = T.n_inline;
+    S.n_bvh = T.n_bvh;
+    S.bvh_depth = T.bvh_depth;
     return SVO_OK;
 }
 
@@ -556,6 +697,7 @@ int svo_create(svo_ctx** out, int device_ordinal) {
     HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device_ordinal));
     c->max_lds = (size_t)lds;
     c->cfg = default_config();
+    HIP_TRY(svo::prepare_trace(c->max_lds));
     HIP_TRY(hipMalloc((void**)&c->d_queue, kMaxStreams * 2 * sizeof(uint32_t)));
     HIP_TRY(hipMemset(c->d_queue, 0, kMaxStreams * 2 * sizeof(uint32_t)));
     HIP_TRY(hipDeviceSynchronize());
@@ -567,6 +709,11 @@ void svo_destroy(svo_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    for (svo_plan* p : ctx->plans) {
+        destroy_plan(*p);
+        delete p;
+    }
+    ctx->plans.clear();
     for (auto& kv : ctx->scenes) free_scene(*kv.second);
     ctx->scenes.clear();
     for (auto& b : ctx->batch) {
@@ -656,6 +803,8 @@ int svo_free_scene(svo_ctx* ctx, svo_scene scene) {
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     auto it = ctx->scenes.find(scene);
     if (it == ctx->scenes.end()) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    for (const svo_plan* p : ctx->plans)
+        if (p->scenes.count(scene)) return fail(SVO_EBUSY, "scene %u belongs to a live plan", scene);
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipDeviceSynchronize());
     free_scene(*it->second);
@@ -779,6 +928,117 @@ void fill_common(const svo_config& c, svo::TraceArgs& a) {
     a.step_limit = c.step_limit;
 }
 
+// Validated jobs of one launch, with their frame and candidate placement.
+struct PackedJob {
+    Scene* S;
+    const svo_job* j;
+    uint32_t frame_base, cand_base, bvh_base;
+    std::vector<unsigned char> table;   // job-specific transforms (else the scene's current table)
+    TableInfo T;
+};
+
+struct Packing {
+    std::vector<PackedJob> jobs;        // non-empty jobs, in order
+    uint64_t total = 0;
+    uint32_t frames = 0, cands = 0, max_cand = 0, stack_levels = 1, nest_levels = 0, bvh = 0, bvh_depth = 0;
+    const uint64_t* cache_src = nullptr;  // the pool with the most rays
+};
+
+// Validate jobs (their scenes restricted to `allowed` when given), build the
+// frame tables of jobs that bring their own transforms, and place every
+// job's frame records and candidates.
+int pack_jobs(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, const std::set<svo_scene>* allowed, Packing& P) {
+    std::map<const uint64_t*, uint64_t> rays_per_pool;
+    for (uint32_t i = 0; i < n_jobs; ++i) {
+        const svo_job& J = jobs[i];
+        Scene* S = find_scene(ctx, J.scene);
+        if (!S) return fail(SVO_EINVAL, "job %u: unknown scene %u", i, J.scene);
+        if (allowed && !allowed->count(J.scene)) return fail(SVO_EINVAL, "job %u: scene %u is not one of the plan's", i, J.scene);
+        if (J.n == 0) continue;
+        if (!J.rays || !J.out_id || !J.out_t) return fail(SVO_EINVAL, "job %u: rays, out_id and out_t are required", i);
+        if (((uintptr_t)J.rays) & 15u) return fail(SVO_EINVAL, "job %u: rays must be 16-byte aligned", i);
+        if (P.jobs.size() >= svo::kMaxJobs) return fail(SVO_ERANGE, "at most %u non-empty jobs per launch", svo::kMaxJobs);
+        PackedJob Q{S, &J, P.frames, P.cands, P.bvh, {}, TableInfo()};
+        if (J.fwd_3x4) {
+            std::vector<Aff> fwd(S->n_slots);
+            for (uint32_t s = 0; s < S->n_slots; ++s) {
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 4; ++c) {
+                        const float v = J.fwd_3x4[12 * s + 4 * r + c];
+                        if (!std::isfinite(v)) return fail(SVO_EINVAL, "job %u: transform of slot %u is not finite", i, s);
+                        fwd[s].m[r][c] = v;
+                    }
+            }
+            Q.table.resize(S->table_bytes);
+            const int rc = build_frames(*S, fwd, Q.table.data(), Q.T);
+            if (rc) return rc;
+        } else {
+            Q.T.n_cand = S->n_cand;
+            Q.T.stack_levels = S->stack_levels;
+            Q.T.nest_levels = S->nest_levels;
+            Q.T.n_bvh = S->n_bvh;
+            Q.T.bvh_depth = S->bvh_depth;
+        }
+        P.frames += S->n_frames;
+        P.cands += Q.T.n_cand;
+        P.bvh += Q.T.n_bvh;
+        P.bvh_depth = std::max(P.bvh_depth, Q.T.bvh_depth);
+        P.total += J.n;
+        if (P.total > 0xFF000000ull) return fail(SVO_ERANGE, "at most 0xff000000 rays per launch");
+        P.max_cand = std::max(P.max_cand, Q.T.n_cand);
+        P.stack_levels = std::max(P.stack_levels, Q.T.stack_levels);
+        P.nest_levels = std::max(P.nest_levels, Q.T.nest_levels);
+        rays_per_pool[S->d_nodes] += J.n;
+        P.jobs.push_back(std::move(Q));
+    }
+    uint64_t best = 0;
+    for (auto& kv : rays_per_pool)
+        if (kv.second > best) {
+            best = kv.second;
+            P.cache_src = kv.first;
+        }
+    return SVO_OK;
+}
+
+// Write job records, frame records, candidates (absolute frame indices) and
+// spheres of a packing into host memory; the jobs of the cached pool get
+// `cache_nodes` LDS nodes.
+void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t* cr, float* sr, svo::BvhNode* br,
+                  uint32_t cache_nodes) {
+    uint64_t begin = 0;
+    for (size_t i = 0; i < P.jobs.size(); ++i) {
+        const PackedJob& Q = P.jobs[i];
+        const Scene& S = *Q.S;
+        const unsigned char* tab = Q.table.empty() ? S.h_stage[S.cur] : Q.table.data();
+        std::memcpy(fr + Q.frame_base, tab, (size_t)S.n_frames * sizeof(svo::FrameRec));
+        std::memcpy(sr + 4 * (size_t)Q.frame_base, tab + sphere_offset(S.n_frames, S.n_slots), (size_t)S.n_frames * 16);
+        const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + cand_offset(S.n_frames));
+        for (uint32_t c = 0; c < Q.T.n_cand; ++c) cr[Q.cand_base + c] = Q.frame_base + sc[c];
+        std::memcpy(br + Q.bvh_base, tab + bvh_offset(S.n_frames, S.n_slots), (size_t)Q.T.n_bvh * sizeof(svo::BvhNode));
+        const svo_job& J = *Q.j;
+        jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
+                            J.out_normal, begin, Q.frame_base, Q.cand_base, Q.T.n_cand,
+                            S.d_nodes == P.cache_src ? cache_nodes : 0u, Q.bvh_base};
+        begin += J.n;
+    }
+}
+
+// Traversal-stack entries a scene can need under any transforms: the walk
+// of an in-place frame stacks on top of its enclosing walks, so bound every
+// frame by its root's depth below the world root plus its height.
+uint32_t stack_bound(const Scene& S) {
+    const Analysis& A = S.an;
+    uint32_t bound = A.world_height + 1;
+    std::vector<uint32_t> absdepth(S.n_slots, 0);
+    for (uint32_t s : A.order) {
+        const int32_t p = A.slot_parent[s];
+        absdepth[s] = (p < 0 ? 0u : absdepth[p]) + A.slot_level[s];
+        bound = std::max(bound, absdepth[s] + A.slot_height[s] + 1);
+    }
+    return bound;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -802,10 +1062,13 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     const uint32_t cache = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, S->n_nodes) & ~1u;
     a.jobs = nullptr;
     a.job0 = svo::JobRec{S->d_nodes, reinterpret_cast<const float4*>(rays), out_id, out_inst, out_t, out_normal,
-                         0, 0, 0, S->n_cand, cache};
+                         0, 0, 0, S->n_cand, cache, 0};
     a.frames = reinterpret_cast<const svo::FrameRec*>(S->d_table[S->cur]);
     a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + cand_offset(S->n_frames));
     a.spheres = reinterpret_cast<const float4*>(S->d_table[S->cur] + sphere_offset(S->n_frames, S->n_slots));
+    a.bvh = reinterpret_cast<const svo::BvhNode*>(S->d_table[S->cur] + bvh_offset(S->n_frames, S->n_slots));
+    a.n_bvh_total = S->n_bvh;
+    a.bvh_depth = S->bvh_depth;
     a.n_jobs = 1;
     a.n_frames = S->n_frames;
     a.n_cand_total = S->n_cand;
@@ -825,80 +1088,56 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     if (n_jobs && !jobs) return fail(SVO_EINVAL, "jobs is NULL");
     try {
-        // validate and size
-        struct Plan {
-            Scene* S;
-            const svo_job* j;
-            uint32_t frame_base, cand_base;
-            std::vector<unsigned char> table;   // job-specific transforms (else the scene's current table)
-            TableInfo T;
-        };
-        std::vector<Plan> plan;
-        uint64_t total = 0;
-        uint32_t frames = 0, cands = 0;
-        std::map<const uint64_t*, uint64_t> rays_per_pool;
-        for (uint32_t i = 0; i < n_jobs; ++i) {
-            const svo_job& J = jobs[i];
-            Scene* S = find_scene(ctx, J.scene);
-            if (!S) return fail(SVO_EINVAL, "job %u: unknown scene %u", i, J.scene);
-            if (J.n == 0) continue;
-            if (!J.rays || !J.out_id || !J.out_t) return fail(SVO_EINVAL, "job %u: rays, out_id and out_t are required", i);
-            if (((uintptr_t)J.rays) & 15u) return fail(SVO_EINVAL, "job %u: rays must be 16-byte aligned", i);
-            Plan P{S, &J, frames, cands, {}, TableInfo()};
-            if (J.fwd_3x4) {
-                std::vector<Aff> fwd(S->n_slots);
-                for (uint32_t s = 0; s < S->n_slots; ++s) {
-                    for (int r = 0; r < 3; ++r)
-                        for (int c = 0; c < 4; ++c) {
-                            const float v = J.fwd_3x4[12 * s + 4 * r + c];
-                            if (!std::isfinite(v)) return fail(SVO_EINVAL, "job %u: transform of slot %u is not finite", i, s);
-                            fwd[s].m[r][c] = v;
-                        }
-                }
-                P.table.resize(S->table_bytes);
-                const int rc = build_frames(*S, fwd, P.table.data(), P.T);
-                if (rc) return rc;
-            } else {
-                P.T.n_cand = S->n_cand;
-                P.T.stack_levels = S->stack_levels;
-                P.T.nest_levels = S->nest_levels;
-            }
-            frames += S->n_frames;
-            cands += P.T.n_cand;
-            total += J.n;
-            rays_per_pool[S->d_nodes] += J.n;
-            plan.push_back(std::move(P));
-        }
-        if (plan.empty()) return SVO_OK;
-        if (plan.size() > svo::kMaxJobs) return fail(SVO_ERANGE, "at most %u non-empty jobs per batch", svo::kMaxJobs);
-        if (frames > 2047) return fail(SVO_ERANGE, "a batch may hold at most 2047 frame records (has %u)", frames);
-        if (total > 0xFF000000ull) return fail(SVO_ERANGE, "at most 0xff000000 rays per batch");
+        Packing P;
+        int rc = pack_jobs(ctx, jobs, n_jobs, nullptr, P);
+        if (rc) return rc;
+        if (P.jobs.empty()) return SVO_OK;
+        if (P.frames > 2047) return fail(SVO_ERANGE, "a batch may hold at most 2047 frame records (has %u)", P.frames);
         hipStream_t st = (hipStream_t)stream;
         uint32_t qslot;
-        int rc = queue_slot(ctx, st, qslot);
+        rc = queue_slot(ctx, st, qslot);
         if (rc) return rc;
         HIP_TRY(hipSetDevice(ctx->device));
 
-        // node cache: the pool with the most rays in this batch
-        const uint64_t* cache_src = nullptr;
-        uint64_t best = 0;
-        for (auto& kv : rays_per_pool)
-            if (kv.second > best) { best = kv.second; cache_src = kv.first; }
-        uint64_t cache_pool_nodes = 0;
+        // configuration and node cache: the pool with the most rays in this batch
         const svo_config* pcfg = &ctx->cfg;
-        for (auto& P : plan)
-            if (P.S->d_nodes == cache_src) {
-                cache_pool_nodes = P.S->n_nodes;
-                if (P.S->tuned) pcfg = &P.S->cfg;
+        uint64_t cache_pool_nodes = 0;
+        for (auto& J : P.jobs)
+            if (J.S->d_nodes == P.cache_src) {
+                cache_pool_nodes = J.S->n_nodes;
+                if (J.S->tuned) pcfg = &J.S->cfg;
             }
         const svo_config& cfg = *pcfg;
-        const uint32_t cache = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, cache_pool_nodes) & ~1u;
 
-        // pack [jobs][frames][candidates]
-        const size_t jb = plan.size() * sizeof(svo::JobRec);
-        const size_t fb = (size_t)frames * sizeof(svo::FrameRec);
-        const size_t sb = (jb + fb + (size_t)cands * sizeof(uint32_t) + 15) & ~(size_t)15;
-        const size_t bytes = sb + (size_t)frames * 16;
+        // pack [jobs][frames][candidates][spheres][hierarchy nodes]
+        const size_t jb = P.jobs.size() * sizeof(svo::JobRec);
+        const size_t fb = (size_t)P.frames * sizeof(svo::FrameRec);
+        const size_t sb = (jb + fb + (size_t)P.cands * sizeof(uint32_t) + 15) & ~(size_t)15;
+        const size_t bb = sb + (size_t)P.frames * 16;
+        const size_t bytes = bb + (size_t)P.bvh * sizeof(svo::BvhNode);
+        svo::TraceArgs a{};
+        a.n_bvh_total = P.bvh;
+        a.bvh_depth = P.bvh_depth;
+        a.n_jobs = (uint32_t)P.jobs.size();
+        a.n_frames = P.frames;
+        a.n_cand_total = P.cands;
+        a.max_cand = P.max_cand;
+        a.n_rays = P.total;
+        a.cache_src = P.cache_src;
+        a.queue = ctx->d_queue + 2 * qslot;
+        a.lds_nodes = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, cache_pool_nodes) & ~1u;
+        a.sort_cand = P.max_cand <= svo::kMaxSortedCand ? 1u : 0u;
+        a.stack_levels = P.stack_levels;
+        a.nest_levels = P.nest_levels;
+        fill_common(cfg, a);
+        // size LDS now: a smaller node cache changes the jobs' lds_nodes
+        size_t lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
+        while (lds > ctx->max_lds && a.lds_nodes > 0) {
+            a.lds_nodes = (a.lds_nodes / 2) & ~1u;
+            lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
+        }
+        if (lds > ctx->max_lds) return fail(SVO_ERANGE, "batch needs %zu bytes of LDS per work-group", lds);
+
         auto& B = ctx->batch[ctx->next_batch];
         ctx->next_batch = (ctx->next_batch + 1) % 4;
         if (B.ev) HIP_TRY(hipEventSynchronize(B.ev));
@@ -914,52 +1153,14 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
             B.cap = cap;
         }
         if (!B.ev) HIP_TRY(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
-        svo::JobRec* jr = reinterpret_cast<svo::JobRec*>(B.host);
-        svo::FrameRec* fr = reinterpret_cast<svo::FrameRec*>(B.host + jb);
-        uint32_t* cr = reinterpret_cast<uint32_t*>(B.host + jb + fb);
-        float* sr = reinterpret_cast<float*>(B.host + sb);
-        uint64_t begin = 0;
-        svo::TraceArgs a{};
-        uint32_t max_cand = 0;
-        for (size_t i = 0; i < plan.size(); ++i) {
-            Plan& P = plan[i];
-            Scene& S = *P.S;
-            const unsigned char* tab = P.table.empty() ? S.h_stage[S.cur] : P.table.data();
-            std::memcpy(fr + P.frame_base, tab, (size_t)S.n_frames * sizeof(svo::FrameRec));
-            std::memcpy(sr + 4 * (size_t)P.frame_base, tab + sphere_offset(S.n_frames, S.n_slots), (size_t)S.n_frames * 16);
-            const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + cand_offset(S.n_frames));
-            for (uint32_t c = 0; c < P.T.n_cand; ++c) cr[P.cand_base + c] = P.frame_base + sc[c];
-            const svo_job& J = *P.j;
-            jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
-                                J.out_normal, begin, P.frame_base, P.cand_base, P.T.n_cand,
-                                S.d_nodes == cache_src ? cache : 0u};
-            begin += J.n;
-            max_cand = std::max(max_cand, P.T.n_cand);
-            a.stack_levels = std::max(a.stack_levels, P.T.stack_levels);
-            a.nest_levels = std::max(a.nest_levels, P.T.nest_levels);
-        }
+        write_tables(P, reinterpret_cast<svo::JobRec*>(B.host), reinterpret_cast<svo::FrameRec*>(B.host + jb),
+                     reinterpret_cast<uint32_t*>(B.host + jb + fb), reinterpret_cast<float*>(B.host + sb),
+                     reinterpret_cast<svo::BvhNode*>(B.host + bb), a.lds_nodes);
         a.jobs = reinterpret_cast<const svo::JobRec*>(B.dev);
         a.frames = reinterpret_cast<const svo::FrameRec*>(B.dev + jb);
         a.cand = reinterpret_cast<const uint32_t*>(B.dev + jb + fb);
         a.spheres = reinterpret_cast<const float4*>(B.dev + sb);
-        a.n_jobs = (uint32_t)plan.size();
-        a.n_frames = frames;
-        a.n_cand_total = cands;
-        a.max_cand = max_cand;
-        a.n_rays = total;
-        a.cache_src = cache_src;
-        a.queue = ctx->d_queue + 2 * qslot;
-        a.lds_nodes = cache;
-        a.sort_cand = max_cand <= svo::kMaxSortedCand ? 1u : 0u;
-        fill_common(cfg, a);
-        // size LDS now: a smaller node cache changes the jobs' lds_nodes
-        size_t lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
-        while (lds > ctx->max_lds && a.lds_nodes > 0) {
-            a.lds_nodes = (a.lds_nodes / 2) & ~1u;
-            lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
-        }
-        for (size_t i = 0; i < plan.size(); ++i)
-            if (jr[i].lds_nodes) jr[i].lds_nodes = a.lds_nodes;
+        a.bvh = reinterpret_cast<const svo::BvhNode*>(B.dev + bb);
         HIP_TRY(hipMemcpyAsync(B.dev, B.host, bytes, hipMemcpyHostToDevice, st));
         rc = launch(ctx, cfg, a, st);
         if (rc) return rc;
@@ -968,6 +1169,171 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
     } catch (const std::bad_alloc&) {
         return fail(SVO_ENOMEM, "out of host memory");
     }
+}
+
+// ------------------------------------------------------------------ plans
+
+int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, const svo_plan_limits* limits,
+                    svo_plan** out) {
+    if (out) *out = nullptr;
+    if (!ctx || !scenes || !limits || !out) return fail(SVO_EINVAL, "ctx, scenes, limits and out are required");
+    if (n_scenes == 0) return fail(SVO_EINVAL, "a plan needs at least one scene");
+    if (limits->reserved[0] || limits->reserved[1]) return fail(SVO_EINVAL, "reserved limit fields must be zero");
+    if (limits->max_jobs < 1 || limits->max_jobs > svo::kMaxJobs)
+        return fail(SVO_ERANGE, "max_jobs must be 1..%u", svo::kMaxJobs);
+    if (limits->max_frames < 1 || limits->max_frames > 2047) return fail(SVO_ERANGE, "max_frames must be 1..2047");
+    try {
+        std::unique_ptr<svo_plan> pl(new svo_plan());
+        uint32_t max_slots = 0;
+        uint64_t max_pool = 0;
+        for (uint32_t i = 0; i < n_scenes; ++i) {
+            Scene* S = find_scene(ctx, scenes[i]);
+            if (!S) return fail(SVO_EINVAL, "unknown scene %u", scenes[i]);
+            pl->scenes.insert(scenes[i]);
+            pl->stack_cap = std::max(pl->stack_cap, stack_bound(*S));
+            pl->nest_cap = std::max(pl->nest_cap, std::min<uint32_t>(svo::kMaxInlineNest, S->an.max_nesting));
+            max_slots = std::max(max_slots, S->n_slots);
+            max_pool = std::max(max_pool, S->n_nodes);
+        }
+        if (pl->stack_cap > 127) return fail(SVO_ERANGE, "scenes need %u stack levels (limit 127)", pl->stack_cap);
+        Scene* S0 = find_scene(ctx, scenes[0]);
+        pl->cfg = S0->tuned ? S0->cfg : ctx->cfg;
+        pl->max_jobs = limits->max_jobs;
+        pl->max_frames = limits->max_frames;
+        pl->max_cand = std::min(max_slots, limits->max_frames);
+        // table layout: [header][jobs][frames][candidates][spheres], capacities
+        pl->off_jobs = sizeof(svo::LaunchHdr);
+        pl->off_frames = pl->off_jobs + (size_t)pl->max_jobs * sizeof(svo::JobRec);
+        pl->off_cand = pl->off_frames + (size_t)pl->max_frames * sizeof(svo::FrameRec);
+        pl->off_sph = (pl->off_cand + (size_t)pl->max_frames * sizeof(uint32_t) + 15) & ~(size_t)15;
+        pl->off_bvh = pl->off_sph + (size_t)pl->max_frames * 16;
+        pl->max_bvh = 2 * pl->max_frames;
+        pl->bvh_depth_cap = bvh_levels(pl->max_cand);
+        pl->bytes = pl->off_bvh + (size_t)pl->max_bvh * sizeof(svo::BvhNode);
+
+        svo::TraceArgs& a = pl->args;
+        a = svo::TraceArgs{};
+        a.n_jobs = pl->max_jobs;
+        a.n_frames = pl->max_frames;
+        a.n_cand_total = pl->max_frames;
+        a.n_bvh_total = pl->max_bvh;
+        a.bvh_depth = pl->bvh_depth_cap;
+        a.max_cand = pl->max_cand;
+        a.sort_cand = pl->max_cand <= svo::kMaxSortedCand ? 1u : 0u;
+        a.stack_levels = pl->stack_cap;
+        a.nest_levels = pl->nest_cap;
+        a.lds_nodes = (uint32_t)std::min<uint64_t>(pl->cfg.lds_cache_nodes, max_pool) & ~1u;
+        fill_common(pl->cfg, a);
+        size_t lds = svo::trace_lds_bytes(a, pl->cfg.waves_per_block);
+        while (lds > ctx->max_lds && a.lds_nodes > 0) {
+            a.lds_nodes = (a.lds_nodes / 2) & ~1u;
+            lds = svo::trace_lds_bytes(a, pl->cfg.waves_per_block);
+        }
+        if (lds > ctx->max_lds) return fail(SVO_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
+        pl->launch_cfg.waves_per_block = pl->cfg.waves_per_block;
+        pl->launch_cfg.blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ctx->n_cu * pl->cfg.blocks_per_cu);
+        pl->launch_cfg.lds_bytes = lds;
+
+        HIP_TRY(hipSetDevice(ctx->device));
+        auto release = [&]() { destroy_plan(*pl); };
+        if (hipMalloc((void**)&pl->dev, pl->bytes) != hipSuccess ||
+            hipHostMalloc((void**)&pl->host, pl->bytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&pl->d_queue, 2 * sizeof(uint32_t)) != hipSuccess) {
+            release();
+            return fail(SVO_ENOMEM, "plan allocation failed");
+        }
+        std::memset(pl->host, 0, pl->bytes);
+        if (hipMemset(pl->d_queue, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+            hipMemcpy(pl->dev, pl->host, pl->bytes, hipMemcpyHostToDevice) != hipSuccess ||
+            hipEventCreateWithFlags(&pl->ev, hipEventDisableTiming) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess) {
+            release();
+            return fail(SVO_EDEVICE, "plan set-up failed");
+        }
+        a.hdr = reinterpret_cast<const svo::LaunchHdr*>(pl->dev);
+        a.jobs = reinterpret_cast<const svo::JobRec*>(pl->dev + pl->off_jobs);
+        a.frames = reinterpret_cast<const svo::FrameRec*>(pl->dev + pl->off_frames);
+        a.cand = reinterpret_cast<const uint32_t*>(pl->dev + pl->off_cand);
+        a.spheres = reinterpret_cast<const float4*>(pl->dev + pl->off_sph);
+        a.bvh = reinterpret_cast<const svo::BvhNode*>(pl->dev + pl->off_bvh);
+        a.queue = pl->d_queue;
+        *out = pl.get();
+        ctx->plans.insert(pl.release());
+        return SVO_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SVO_ENOMEM, "out of host memory");
+    }
+}
+
+int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_t n_jobs) {
+    if (!ctx || !plan) return fail(SVO_EINVAL, "ctx and plan are required");
+    if (!ctx->plans.count(plan)) return fail(SVO_EINVAL, "plan does not belong to this context");
+    if (n_jobs && !jobs) return fail(SVO_EINVAL, "jobs is NULL");
+    try {
+        Packing P;
+        int rc = pack_jobs(ctx, jobs, n_jobs, &plan->scenes, P);
+        if (rc) return rc;
+        if (P.jobs.size() > plan->max_jobs) return fail(SVO_ERANGE, "%zu jobs, the plan holds %u", P.jobs.size(), plan->max_jobs);
+        if (P.frames > plan->max_frames)
+            return fail(SVO_ERANGE, "%u frame records, the plan holds %u", P.frames, plan->max_frames);
+        if (P.stack_levels > plan->stack_cap || P.nest_levels > plan->nest_cap || P.max_cand > plan->max_cand ||
+            P.bvh > plan->max_bvh || P.bvh_depth > plan->bvh_depth_cap)
+            return fail(SVO_ERANGE, "jobs exceed the plan's stack, nesting or candidate capacity");
+        if (plan->ev_pending) {
+            HIP_TRY(hipSetDevice(ctx->device));
+            HIP_TRY(hipEventSynchronize(plan->ev));
+            plan->ev_pending = false;
+        }
+        unsigned char* H = plan->host;
+        svo::LaunchHdr hdr{};
+        hdr.n_rays = P.total;
+        hdr.n_jobs = (uint32_t)P.jobs.size();
+        hdr.n_frames = P.frames;
+        hdr.n_cand_total = P.cands;
+        hdr.n_bvh_total = P.bvh;
+        uint32_t fill = 0;
+        for (auto& J : P.jobs)
+            if (J.S->d_nodes == P.cache_src) fill = (uint32_t)std::min<uint64_t>(plan->args.lds_nodes, J.S->n_nodes) & ~1u;
+        hdr.cache_src = fill ? P.cache_src : nullptr;
+        hdr.lds_nodes = fill;
+        std::memcpy(H, &hdr, sizeof hdr);
+        write_tables(P, reinterpret_cast<svo::JobRec*>(H + plan->off_jobs), reinterpret_cast<svo::FrameRec*>(H + plan->off_frames),
+                     reinterpret_cast<uint32_t*>(H + plan->off_cand), reinterpret_cast<float*>(H + plan->off_sph),
+                     reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh), fill);
+        return SVO_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SVO_ENOMEM, "out of host memory");
+    }
+}
+
+int svo_plan_launch(svo_ctx* ctx, svo_plan* plan, void* stream) {
+    if (!ctx || !plan) return fail(SVO_EINVAL, "ctx and plan are required");
+    if (!ctx->plans.count(plan)) return fail(SVO_EINVAL, "plan does not belong to this context");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    HIP_TRY(hipMemcpyAsync(plan->dev, plan->host, plan->bytes, hipMemcpyHostToDevice, st));
+    if (cs == hipStreamCaptureStatusNone) {
+        HIP_TRY(hipEventRecord(plan->ev, st));
+        plan->ev_pending = true;
+    }
+    const hipError_t e = svo::launch_trace(plan->args, plan->launch_cfg, st);
+    if (e != hipSuccess) return fail(SVO_EDEVICE, "plan launch failed: %s", hipGetErrorString(e));
+    return SVO_OK;
+}
+
+int svo_plan_destroy(svo_ctx* ctx, svo_plan* plan) {
+    if (!plan) return SVO_OK;
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    if (!ctx->plans.count(plan)) return fail(SVO_EINVAL, "plan does not belong to this context");
+    (void)hipSetDevice(ctx->device);
+    if (plan->ev_pending) (void)hipEventSynchronize(plan->ev);
+    (void)hipDeviceSynchronize();
+    ctx->plans.erase(plan);
+    destroy_plan(*plan);
+    delete plan;
+    return SVO_OK;
 }
 
 int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n, void* stream, svo_config* best) {

@@ -32,8 +32,24 @@ enum : uint32_t {
 
 // Frames entered in place may nest this deep inside one top-level frame.
 constexpr uint32_t kMaxInlineNest = 4;
-// Per-lane candidate entry tables are kept in LDS up to this many candidates.
+// Per-lane candidate entry tables are kept in LDS up to this many candidates;
+// beyond, candidates are found through a bounding-box hierarchy.
 constexpr uint32_t kMaxSortedCand = 16;
+
+// One node of a frame table's hierarchy over its candidate frames: the
+// world-space box of the moved root cells below it (widened outward so that
+// FP32 slab tests never lose a hit).  Interior: a = left child, b = right
+// child (node indices within the table's hierarchy).  Leaf: b = kBvhLeaf |
+// count, a = first entry in the table's candidate list.  32 bytes.
+struct alignas(16) BvhNode {
+    float lo[3];
+    uint32_t a;
+    float hi[3];
+    uint32_t b;
+};
+static_assert(sizeof(BvhNode) == 32, "hierarchy node must be 32 bytes");
+constexpr uint32_t kBvhLeaf = 0x80000000u;
+constexpr uint32_t kBvhLeafMax = 2;     // candidates per leaf
 
 // One job of a launch: a ray range traced against one scene under one set
 // of transforms (80 bytes, held in LDS).
@@ -49,17 +65,40 @@ struct alignas(16) JobRec {
     uint32_t cand_base;       // the job's first entry in the launch's candidate list
     uint32_t n_cand;
     uint32_t lds_nodes;       // pool prefix of this job's scene held in LDS (0: none)
+    uint32_t bvh_base;        // the job's hierarchy root in the launch's node array
 };
 static_assert(sizeof(JobRec) == 80, "job record must be 80 bytes");
 
 constexpr uint32_t kMaxJobs = 256;
 
+// Launch-wide counts of a plan launch, read by the kernel from the head of
+// the plan's device table: a captured launch keeps its arguments across
+// replays, so whatever changes between replays lives in device memory.
+struct alignas(16) LaunchHdr {
+    uint64_t n_rays;              // all jobs
+    const uint64_t* cache_src;    // pool whose prefix is cached in LDS (nullptr: none)
+    uint32_t n_jobs;              // <= TraceArgs::n_jobs (the capacity)
+    uint32_t n_frames;            // <= TraceArgs::n_frames
+    uint32_t n_cand_total;        // <= TraceArgs::n_cand_total
+    uint32_t lds_nodes;           // <= TraceArgs::lds_nodes, even
+    uint32_t n_bvh_total;         // <= TraceArgs::n_bvh_total
+    uint32_t pad[7];
+};
+static_assert(sizeof(LaunchHdr) == 64, "launch header must be 64 bytes");
+
+// In a plan launch (hdr != nullptr) n_jobs, n_frames, n_cand_total,
+// n_bvh_total and lds_nodes are capacities that size the LDS layout, and the header holds
+// the counts; n_rays and cache_src are ignored.
 struct TraceArgs {
+    const LaunchHdr* hdr;     // plan launches: counts in device memory; else nullptr
     const JobRec* jobs;       // device job table, or nullptr: the single job in job0
     JobRec job0;
     const FrameRec* frames;   // n_frames records; job j's slot s is frames[frame_base_j + 1 + s]
     const uint32_t* cand;     // candidate frames (absolute indices), per job contiguous
     const float4* spheres;    // n_frames world bounding spheres (centre, radius) of the moved root cells
+    const BvhNode* bvh;       // n_bvh_total hierarchy nodes, per job contiguous (job j's root at bvh_base_j)
+    uint32_t n_bvh_total;
+    uint32_t bvh_depth;       // hierarchy stack entries per lane (used when sort_cand == 0)
     uint32_t n_jobs;
     uint32_t n_frames;
     uint32_t n_cand_total;
@@ -108,6 +147,10 @@ struct AoArgs {
 hipError_t launch_ao_rays(const AoArgs& a, hipStream_t stream);
 
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block);
+// Allow the trace kernel up to max_lds bytes of dynamic LDS on the current
+// device; done once when a context is created, so that no launch (eager or
+// captured into a graph) changes the kernel's attributes.
+hipError_t prepare_trace(size_t max_lds);
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream);
 
 }  // namespace svo

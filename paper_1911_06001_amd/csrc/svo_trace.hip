@@ -15,9 +15,10 @@
 //      cell, switch into that node's frame in place (Sec. 3, Fig. 1: the ray,
 //      not the model, is transformed) and resume the enclosing walk after it;
 //   5. transformed subtrees that leave their static cell are candidates,
-//      traced from their own roots in order of root-cell entry and skipped
-//      once the entry lies beyond the best hit (the depth sort of Sec. 4.2,
-//      with an exact slab test in place of the bounding sphere of Sec. 4.1);
+//      traced from their own roots and skipped once their entry lies beyond
+//      the best hit (the depth sort of Sec. 4.2): up to 16 in order of exact
+//      root-cell entry after the bounding-sphere test of Sec. 4.1, more
+//      through a hierarchy of their world boxes, nearer boxes first;
 //   6. write id, slot, t and the normal (entry face, inverse transpose).
 //
 // Work distribution: a persistent grid.  Each wave keeps 64 rays in flight
@@ -112,6 +113,18 @@ __device__ __forceinline__ bool sphere_may_hit(const float4 sp, const Ray& r, fl
     return (tc - half <= tlimit) && (tc + half >= r.tmin);
 }
 
+// Entry t of the ray into a hierarchy box over [tmin, tlimit], +inf when the
+// box is missed or entered beyond tlimit (i*: inverse world direction).
+__device__ __forceinline__ float box_entry(const BvhNode& B, const Ray& r, float ix, float iy, float iz,
+                                           float tlimit) {
+    const float ax = (B.lo[0] - r.ox) * ix, bx = (B.hi[0] - r.ox) * ix;
+    const float ay = (B.lo[1] - r.oy) * iy, by = (B.hi[1] - r.oy) * iy;
+    const float az = (B.lo[2] - r.oz) * iz, bz = (B.hi[2] - r.oz) * iz;
+    const float t0 = fmaxf(max3f(fminf(ax, bx), fminf(ay, by), fminf(az, bz)), r.tmin);
+    const float t1 = fminf(min3f(fmaxf(ax, bx), fmaxf(ay, by), fmaxf(az, bz)), tlimit);
+    return (t0 <= t1) ? t0 : INFINITY;
+}
+
 __device__ __forceinline__ bool ray_valid(const Ray& r) {
     const bool fin = isfinite(r.ox) && isfinite(r.oy) && isfinite(r.oz) && isfinite(r.dx) && isfinite(r.dy) &&
                      isfinite(r.dz);
@@ -137,11 +150,17 @@ __device__ __forceinline__ void gst(T* p, uint64_t i, T v) {
 
 }  // namespace
 
+// Per-lane candidate state in LDS: the entry table (sorted path) or the
+// hierarchy stack of (node, entry t) pairs, one more than its levels.
+__host__ __device__ __forceinline__ size_t cand_lane_bytes(const TraceArgs& a) {
+    return a.sort_cand ? (size_t)a.max_cand * 4 : (a.max_cand ? (size_t)(a.bvh_depth + 1) * 8 : 0);
+}
+
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
     const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 80 +
-                          align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec);
-    const size_t per_wave = (a.sort_cand ? (size_t)a.max_cand * 64 * 4 : 0) + (size_t)a.stack_levels * 64 * 8 +
-                            (size_t)a.nest_levels * 64 * 16;
+                          align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec) +
+                          (size_t)a.n_bvh_total * sizeof(BvhNode);
+    const size_t per_wave = cand_lane_bytes(a) * 64 + (size_t)a.stack_levels * 64 * 8 + (size_t)a.nest_levels * 64 * 16;
     return shared + per_wave * waves_per_block;
 }
 
@@ -158,27 +177,54 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     p += align16((size_t)a.n_cand_total * 4);
     JobRec* lds_jobs = reinterpret_cast<JobRec*>(p);
     p += (size_t)a.n_jobs * sizeof(JobRec);
+    BvhNode* lds_bvh = reinterpret_cast<BvhNode*>(p);
+    p += (size_t)a.n_bvh_total * sizeof(BvhNode);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    const size_t ent_bytes = a.sort_cand ? (size_t)a.max_cand * 64 * 4 : 0;
+    const size_t ent_bytes = cand_lane_bytes(a) * 64;
     const size_t per_wave = ent_bytes + (size_t)a.stack_levels * 64 * 8 + (size_t)a.nest_levels * 64 * 16;
+    const uint32_t bst_cap = a.bvh_depth + 1;
     unsigned char* wp = p + per_wave * wave;
     float* ent = reinterpret_cast<float*>(wp) + lane;                                   // candidate c at ent[c * 64]
+    uint2* bst = reinterpret_cast<uint2*>(wp) + lane;                                   // hierarchy entry k at bst[k * 64]
     uint2* stk = reinterpret_cast<uint2*>(wp + ent_bytes) + lane;                       // level l at stk[l * 64]
     uint4* fst = reinterpret_cast<uint4*>(wp + ent_bytes + (size_t)a.stack_levels * 512) + lane;  // nest n at fst[n * 64]
 
-    for (uint32_t i = threadIdx.x; i < a.lds_nodes; i += blockDim.x) lds_nodes[i] = a.cache_src[i];
+    // launch-wide counts: the arguments, or a plan's header (capacities
+    // above bound them, so every LDS copy below stays in its region)
+    uint64_t n_rays = a.n_rays;
+    uint32_t n_jobs = a.n_jobs, n_frames = a.n_frames, n_cand_total = a.n_cand_total, fill_nodes = a.lds_nodes;
+    uint32_t n_bvh = a.n_bvh_total;
+    const uint64_t* cache_src = a.cache_src;
+    if (a.hdr) {
+        const LaunchHdr& h = *a.hdr;
+        n_rays = h.n_rays;
+        n_jobs = min(h.n_jobs, a.n_jobs);
+        n_frames = min(h.n_frames, a.n_frames);
+        n_cand_total = min(h.n_cand_total, a.n_cand_total);
+        fill_nodes = min(h.lds_nodes, a.lds_nodes);
+        n_bvh = min(h.n_bvh_total, a.n_bvh_total);
+        cache_src = h.cache_src;
+        if (!cache_src) fill_nodes = 0;
+        if (n_jobs == 0) n_rays = 0;
+    }
+    for (uint32_t i = threadIdx.x; i < fill_nodes; i += blockDim.x) lds_nodes[i] = cache_src[i];
     {
         const uint4* src = reinterpret_cast<const uint4*>(a.frames);
         uint4* dst = reinterpret_cast<uint4*>(lds_frames);
-        for (uint32_t i = threadIdx.x; i < a.n_frames * 4u; i += blockDim.x) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < n_frames * 4u; i += blockDim.x) dst[i] = src[i];
     }
-    for (uint32_t i = threadIdx.x; i < a.n_frames; i += blockDim.x) lds_sph[i] = a.spheres[i];
-    for (uint32_t i = threadIdx.x; i < a.n_cand_total; i += blockDim.x) lds_cand[i] = a.cand[i];
+    for (uint32_t i = threadIdx.x; i < n_frames; i += blockDim.x) lds_sph[i] = a.spheres[i];
+    for (uint32_t i = threadIdx.x; i < n_cand_total; i += blockDim.x) lds_cand[i] = a.cand[i];
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(a.bvh);
+        uint4* dst = reinterpret_cast<uint4*>(lds_bvh);
+        for (uint32_t i = threadIdx.x; i < n_bvh * 2u; i += blockDim.x) dst[i] = src[i];
+    }
     if (a.jobs) {
         const uint4* src = reinterpret_cast<const uint4*>(a.jobs);
         uint4* dst = reinterpret_cast<uint4*>(lds_jobs);
-        for (uint32_t i = threadIdx.x; i < a.n_jobs * (uint32_t)(sizeof(JobRec) / 16); i += blockDim.x) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < n_jobs * (uint32_t)(sizeof(JobRec) / 16); i += blockDim.x) dst[i] = src[i];
     } else if (threadIdx.x == 0) {
         lds_jobs[0] = a.job0;
     }
@@ -196,7 +242,9 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     float best_t = INFINITY, tl = 0.f;
     uint32_t best_id = kNone, best_inst = kNone;
     int best_f = -1, best_axis = 3;
-    uint32_t steps = 0, cnext = 0;
+    uint32_t steps = 0;
+    uint32_t bbase = 0, bsp = 0, leaf_i = 0, leaf_end = 0;   // hierarchy walk over the candidates
+    float wix = 0.f, wiy = 0.f, wiz = 0.f;                   // inverse world direction
     FrameRay fr{};
     uint32_t cur_f = 0, pmask = 0, pchild = 0, px = 0, py = 0, pz = 0, size = 1, lvl = 1, sbase = 0, nest = 0;
     float tc0 = 0.f;
@@ -280,14 +328,14 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
             uint32_t base = 0;
             if (lane == leader) base = atomicAdd(&a.queue[0], nidle);
             base = __shfl(base, (int)leader);
-            if ((uint64_t)base + nidle >= a.n_rays) exhausted = true;
+            if ((uint64_t)base + nidle >= n_rays) exhausted = true;
             if (mode == M_DONE) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 const uint64_t gidx = (uint64_t)base + rank;
-                if (gidx < a.n_rays) {
+                if (gidx < n_rays) {
                     // the job holding this launch-wide ray index (jobs are in ray order)
-                    uint32_t lo = 0, hi = a.n_jobs;
+                    uint32_t lo = 0, hi = n_jobs;
                     while (hi - lo > 1u) {
                         const uint32_t mid = (lo + hi) >> 1;
                         if (lds_jobs[mid].ray_begin <= gidx) lo = mid; else hi = mid;
@@ -296,10 +344,11 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                     const JobRec& J = lds_jobs[job];
                     ri = gidx - J.ray_begin;
                     nodes = J.nodes;
-                    n_lds = J.lds_nodes;
+                    n_lds = min(J.lds_nodes, fill_nodes);
                     fbase = J.frame_base;
                     cbase = J.cand_base;
                     ncand = J.n_cand;
+                    bbase = J.bvh_base;
                     const v4f* rp = reinterpret_cast<const v4f*>(J.rays);
                     const v4f r0 = gld(rp, 2 * ri);
                     const v4f r1 = gld(rp, 2 * ri + 1);
@@ -310,7 +359,9 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                     best_f = -1;
                     best_axis = 3;
                     steps = 0;
-                    cnext = 0;
+                    bsp = 0;
+                    leaf_i = 0;
+                    leaf_end = 0;
                     if (!ray_valid(r)) {
                         finish();
                     } else {
@@ -326,6 +377,17 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                                     if (frame_setup(lds_frames[f], r, tl, cfr, t0, ea)) e = t0;
                                 }
                                 ent[c * 64] = e;
+                            }
+                        } else if (ncand) {
+                            // tiny components clamped as in frame_setup, so no 0 * inf
+                            const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
+                            wix = 1.0f / (fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
+                            wiy = 1.0f / (fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
+                            wiz = 1.0f / (fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
+                            const float e = box_entry(lds_bvh[bbase], r, wix, wiy, wiz, tl);
+                            if (e < INFINITY) {
+                                bst[0] = make_uint2(0u, __float_as_uint(e));
+                                bsp = 1;
                             }
                         }
                         mode = start_frame(fbase) ? M_WALK : M_SELECT;
@@ -510,16 +572,45 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                     if (start_frame(lds_cand[cbase + pick])) mode = M_WALK;
                 }
             } else {
-                // candidates in index order; the sphere test (Sec. 4.1) rejects
-                // most before the exact setup
+                // candidates through the job's hierarchy of their world
+                // boxes, nearer child first, each box skipped once its entry
+                // lies beyond the best hit; a leaf's candidates then pass the
+                // sphere test (Sec. 4.1) before their exact root-cell entry
                 bool started = false;
-                while (cnext < ncand && !started) {
-                    const uint32_t f = lds_cand[cbase + cnext++];
-                    if (sphere_may_hit(lds_sph[f], r, tl)) started = start_frame(f);
+                while (!started) {
+                    if (leaf_i < leaf_end) {
+                        const uint32_t f = lds_cand[cbase + leaf_i++];
+                        if (sphere_may_hit(lds_sph[f], r, tl)) started = start_frame(f);
+                        continue;
+                    }
+                    if (bsp == 0u) break;
+                    --bsp;
+                    const uint2 e = bst[bsp * 64];
+                    if (__uint_as_float(e.y) > tl) continue;
+                    const BvhNode& N = lds_bvh[bbase + e.x];
+                    if (N.b & kBvhLeaf) {
+                        leaf_i = N.a;
+                        leaf_end = N.a + (N.b & 0xFFFFu);
+                        continue;
+                    }
+                    const float eL = box_entry(lds_bvh[bbase + N.a], r, wix, wiy, wiz, tl);
+                    const float eR = box_entry(lds_bvh[bbase + N.b], r, wix, wiy, wiz, tl);
+                    const bool left_near = eL <= eR;
+                    const float en = left_near ? eL : eR, ef = left_near ? eR : eL;
+                    const uint32_t nn = left_near ? N.a : N.b, nf = left_near ? N.b : N.a;
+                    // the far child first, so the near one is popped next
+                    if (ef < INFINITY && bsp < bst_cap) {
+                        bst[bsp * 64] = make_uint2(nf, __float_as_uint(ef));
+                        ++bsp;
+                    }
+                    if (en < INFINITY && bsp < bst_cap) {
+                        bst[bsp * 64] = make_uint2(nn, __float_as_uint(en));
+                        ++bsp;
+                    }
                 }
                 if (started) {
                     mode = M_WALK;
-                } else if (cnext >= ncand) {
+                } else {
                     finish();
                 }
             }
@@ -538,12 +629,12 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     }
 }
 
+hipError_t prepare_trace(size_t max_lds) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds);
+}
+
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream) {
-    if (c.lds_bytes > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds_bytes);
-        if (e != hipSuccess) return e;
-    }
     hipLaunchKernelGGL(trace_kernel, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
     return hipGetLastError();
 }

@@ -7,10 +7,13 @@ resident; a request only brings its ray and output buffers.
 
   batched  requests are admitted while their footprint fits the budget;
            every step packs up to `max_rays_per_step` rays from the admitted
-           requests (first come, first served; large requests are split
-           across steps) into one svo_trace_batch launch, each job with its
-           own scene and animation frame; two steps are kept in flight so the
-           host prepares step k+1 while the device runs step k.
+           requests (large requests are split across steps) into one
+           persistent launch, each job with its own scene and animation
+           frame; two steps are kept in flight so the host prepares step k+1
+           while the device runs step k.  With graph=True each in-flight slot
+           owns a launch plan (svo_plan_*) whose launch was captured once into
+           a HIP graph; a step writes its jobs into the plan's staging and
+           replays the graph.  Otherwise a step is one svo_trace_batch call.
   single   the baseline: one request per svo_trace_rays launch, first come,
            first served, the next one starting when the previous finished.
 
@@ -90,18 +93,26 @@ class Scheduler:
     admit(): move waiting requests (first come, first served) into the
     active set while their footprint fits the budget.  plan(): pick the next
     step's chunks, at most `max_rays` rays, `max_jobs` chunks and `max_frames`
-    frame records (a launch's limits), oldest admitted request first:
-      fifo  each request takes what is left of the step's rays in turn;
+    frame records (a launch's limits):
+      fifo  oldest admitted request first, each taking what is left of the
+            step's rays in turn;
       fair  the step's rays are shared evenly among the requests with work
             left (at least `min_chunk` each), so a small request admitted
             behind a large one finishes in the next step instead of waiting
-            for the large one to drain.
+            for the large one to drain (processor sharing: large requests
+            are stretched by everything that arrives while they run);
+      edf   earliest deadline first, deadline = arrival + slack x rays /
+            ref_rate: a small request overtakes large ones that arrived a
+            little earlier, but no request is passed by work that arrived
+            after its deadline, which bounds the stretch of large requests.
     """
 
-    def __init__(self, budget: int, max_rays: int, policy: str = "fair", min_chunk: int = 1 << 16,
-                 max_jobs: int = 256, max_frames: int = 2047):
-        if policy not in ("fifo", "fair"):
+    def __init__(self, budget: int, max_rays: int, policy: str = "edf", min_chunk: int = 1 << 16,
+                 max_jobs: int = 256, max_frames: int = 2047, slack: float = 3.0, ref_rate: float = 4e9):
+        if policy not in ("fifo", "fair", "edf"):
             raise ValueError(policy)
+        self.slack = float(slack)
+        self.ref_rate = float(ref_rate)
         self.budget = int(budget)
         self.max_rays = int(max_rays)
         self.policy = policy
@@ -129,6 +140,8 @@ class Scheduler:
     def plan(self, active: list) -> list:
         """[(active, lo, hi)] within the step limits; advances next_ray."""
         work = [a for a in active if a.req.rays > a.next_ray]
+        if self.policy == "edf":
+            work.sort(key=lambda a: a.req.arrival + self.slack * a.req.rays / self.ref_rate)
         chunks, left, frames = [], self.max_rays, 0
         share = left
         if self.policy == "fair" and work:
@@ -164,7 +177,7 @@ def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: 
 class Server:
     def __init__(self, ctx: svo.Context, scenes: Dict[str, SceneEntry], hbm_budget: int,
                  max_rays_per_step: int = 1 << 22, inflight_steps: int = 2, keep_outputs: bool = False,
-                 policy: str = "fair"):
+                 policy: str = "edf", graph: bool = False, max_jobs: int = 64, max_frames: int = 512):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -177,6 +190,38 @@ class Server:
         self.stream = torch.cuda.current_stream()
         self.dev = torch.device("cuda:%d" % ctx.device)
         self.frames = {k: 1 + ctx.scene_stats(e.handle).n_slots for k, e in scenes.items()}
+        self.max_jobs = int(max_jobs)
+        self.max_frames = int(max_frames)
+        self.graph = bool(graph)
+        self._plans = []
+        self._graphs = []
+        if self.graph:
+            self._capture()
+
+    def _capture(self):
+        """One plan per in-flight slot, its launch captured into a graph."""
+        t = self.torch
+        handles = [e.handle for e in self.scenes.values()]
+        # the scene with the most pool nodes first: its prefix sizes the LDS cache
+        handles.sort(key=lambda h: -self.ctx.scene_stats(h).device_bytes)
+        for _ in range(self.inflight_steps):
+            plan = self.ctx.plan(handles, max_jobs=self.max_jobs, max_frames=self.max_frames)
+            plan.set_jobs([])
+            g = t.cuda.CUDAGraph()
+            side = t.cuda.Stream()
+            side.wait_stream(t.cuda.current_stream())
+            with t.cuda.graph(g, stream=side):
+                plan.launch(t.cuda.current_stream())
+            self._plans.append(plan)
+            self._graphs.append(g)
+        t.cuda.synchronize()
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        self._graphs = []
+        for p in self._plans:
+            p.close()
+        self._plans = []
 
     # -- helpers
     def _camera(self, req: Request):
@@ -205,7 +250,8 @@ class Server:
         active: List[_Active] = []
         inflight = collections.deque()   # (event, [(active, n_rays)])
         results: List[Result] = []
-        sched = Scheduler(self.budget, self.max_rays, self.policy)
+        sched = Scheduler(self.budget, self.max_rays, self.policy, max_jobs=self.max_jobs, max_frames=self.max_frames)
+        step = 0
         self.scheduler = sched
         t.cuda.synchronize()
         start_ev = t.cuda.Event(enable_timing=True)
@@ -248,7 +294,16 @@ class Server:
                                  out_id=a.out["out_id"][lo:hi], out_inst=a.out["out_inst"][lo:hi],
                                  out_t=a.out["out_t"][lo:hi], out_normal=a.out["out_normal"][lo:hi])
                             for a, lo, hi in chunks]
-                    self.ctx.trace_batch(jobs, stream=self.stream)
+                    if self.graph:
+                        # this slot's previous replay has retired (at most
+                        # inflight_steps - 1 steps are still in flight)
+                        k = step % self.inflight_steps
+                        self._plans[k].set_jobs(jobs)
+                        with t.cuda.stream(self.stream):
+                            self._graphs[k].replay()
+                    else:
+                        self.ctx.trace_batch(jobs, stream=self.stream)
+                    step += 1
                     ev = t.cuda.Event(enable_timing=True)
                     ev.record(self.stream)
                     inflight.append((ev, chunks))

@@ -28,7 +28,7 @@ MAX_INLINE_NEST = 4
 EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
            "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
-           "svo_generate_ao_rays")
+           "svo_generate_ao_rays", "svo_plan_create", "svo_plan_set_jobs", "svo_plan_launch", "svo_plan_destroy")
 
 
 class SvoError(RuntimeError):
@@ -73,6 +73,10 @@ def make_camera(eye, target, up, vfov_deg, width, height, samples=1, seed=0, jit
     c.width, c.height, c.samples, c.seed = int(width), int(height), int(samples), int(seed) & 0xFFFFFFFF
     c.jitter, c.tiled = int(bool(jitter)), int(bool(tiled))
     return c
+
+
+class PlanLimits(ctypes.Structure):
+    _fields_ = [("max_jobs", ctypes.c_uint32), ("max_frames", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class SceneStats(ctypes.Structure):
@@ -120,6 +124,10 @@ def lib():
         "svo_generate_ao_rays": (I, [P, P, P, P, U64, U32, U32, ctypes.c_float, ctypes.c_float, P, P]),
         "svo_get_config": (I, [P, ctypes.POINTER(Config)]),
         "svo_set_config": (I, [P, ctypes.POINTER(Config)]),
+        "svo_plan_create": (I, [P, P, U32, ctypes.POINTER(PlanLimits), ctypes.POINTER(P)]),
+        "svo_plan_set_jobs": (I, [P, P, ctypes.POINTER(Job), U32]),
+        "svo_plan_launch": (I, [P, P, P]),
+        "svo_plan_destroy": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -167,6 +175,54 @@ class Hits:
     inst: "torch.Tensor"
     t: "torch.Tensor"
     normal: "torch.Tensor"
+
+
+def _job_array(jobs):
+    arr = (Job * max(len(jobs), 1))()
+    keep = []
+    for i, j in enumerate(jobs):
+        fwd = j.get("fwd")
+        if fwd is not None:
+            fwd = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
+            keep.append(fwd)
+        r = j["rays"]
+        arr[i] = Job(int(j["scene"]), _np_ptr(fwd) if fwd is not None else None, r.data_ptr(), r.shape[0],
+                     j["out_id"].data_ptr(), j["out_inst"].data_ptr() if j.get("out_inst") is not None else None,
+                     j["out_t"].data_ptr(),
+                     j["out_normal"].data_ptr() if j.get("out_normal") is not None else None)
+    return arr, keep
+
+
+class Plan:
+    """svo_plan_*: fixed-argument batched launch.  set_jobs() packs jobs into
+    the plan's pinned staging; launch() enqueues the staging copy and the
+    persistent trace kernel and may be captured into a torch CUDA graph."""
+
+    def __init__(self, ctx: "Context", scenes, max_jobs: int, max_frames: int):
+        self.ctx = ctx
+        hs = (ctypes.c_uint32 * len(scenes))(*[int(h) for h in scenes])
+        lim = PlanLimits(int(max_jobs), int(max_frames))
+        ptr = ctypes.c_void_p()
+        _check(lib().svo_plan_create(ctx._ptr, hs, len(scenes), ctypes.byref(lim), ctypes.byref(ptr)))
+        self._ptr = ptr
+
+    def set_jobs(self, jobs):
+        arr, keep = _job_array(jobs)
+        _check(lib().svo_plan_set_jobs(self.ctx._ptr, self._ptr, arr, len(jobs)))
+
+    def launch(self, stream=None):
+        _check(lib().svo_plan_launch(self.ctx._ptr, self._ptr, _stream_handle(stream)))
+
+    def close(self):
+        if self._ptr and self.ctx._ptr:
+            lib().svo_plan_destroy(self.ctx._ptr, self._ptr)
+        self._ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Context:
@@ -221,7 +277,7 @@ class Context:
 
     def upload_scene(self, scene, static: bool = False) -> int:
         """Upload a generated scene (svogen.scenes.Scene) or its static twin."""
-        nodes = scene.static_nodes if static else scene.nodes
+        nodes = scene.static_pool() if static else scene.nodes
         return self.upload(nodes, scene.root, scene.root_min, scene.root_size, scene.max_depth, scene.slot_child,
                            scene.slot_cell)
 
@@ -283,19 +339,12 @@ class Context:
     def trace_batch(self, jobs, stream=None):
         """jobs: sequence of dicts with keys scene, rays (device [n, 8]), out_id,
         out_t, and optionally out_inst, out_normal, fwd (host [n_slots, 12])."""
-        arr = (Job * max(len(jobs), 1))()
-        keep = []
-        for i, j in enumerate(jobs):
-            fwd = j.get("fwd")
-            if fwd is not None:
-                fwd = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
-                keep.append(fwd)
-            r = j["rays"]
-            arr[i] = Job(int(j["scene"]), _np_ptr(fwd) if fwd is not None else None, r.data_ptr(), r.shape[0],
-                         j["out_id"].data_ptr(), j["out_inst"].data_ptr() if j.get("out_inst") is not None else None,
-                         j["out_t"].data_ptr(),
-                         j["out_normal"].data_ptr() if j.get("out_normal") is not None else None)
+        arr, keep = _job_array(jobs)
         _check(lib().svo_trace_batch(self._ptr, arr, len(jobs), _stream_handle(stream)))
+
+    def plan(self, scenes, max_jobs: int = 64, max_frames: int = 512) -> "Plan":
+        """A reusable (graph-capturable) batched launch for jobs on `scenes`."""
+        return Plan(self, scenes, max_jobs, max_frames)
 
     def trace(self, scene: int, rays, stream=None, normals: bool = True) -> Hits:
         import torch

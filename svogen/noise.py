@@ -105,3 +105,49 @@ def fbm3_grid(n: int, octaves: int, period0: float, seed: int, dtype=np.float32)
         amp_sum += amp
     total /= dtype(amp_sum)
     return total
+
+
+def value_noise2_grid(n: int, period: float, octave: int, seed: int):
+    """value_noise2 at every column centre (i + 1/2, k + 1/2) of an n x n grid
+    by separable interpolation (lattice values hashed once, blended along x
+    then z with value_noise2's weights and operation order: equal to the
+    pointwise evaluation bit for bit)."""
+    g = (np.arange(n, dtype=np.float64) + 0.5) / period
+    i0 = np.floor(g)
+    w = _smooth(g - i0)
+    i0 = i0.astype(np.int64)
+    lo, hi = int(i0.min()), int(i0.max()) + 1
+    L = np.arange(lo, hi + 1, dtype=np.int64)
+    V = to_signed_unit(hash_keys(L[:, None], L[None, :], octave, seed, 2))   # [x lattice, z lattice]
+    ix = i0 - lo
+    a = V[ix][:, ix] * (1 - w)[:, None] + V[ix + 1][:, ix] * w[:, None]          # lat(0,0)(1-fu) + lat(1,0)fu
+    b = V[ix][:, ix + 1] * (1 - w)[:, None] + V[ix + 1][:, ix + 1] * w[:, None]  # lat(0,1)(1-fu) + lat(1,1)fu
+    return a * (1 - w)[None, :] + b * w[None, :]
+
+
+def fbm2_grid(n: int, octaves: int, period0: float, seed: int):
+    """fbm2 at every column centre of an n x n grid (bit for bit)."""
+    total = np.zeros((n, n))
+    amp_sum = 0.0
+    for o in range(octaves):
+        amp = 2.0 ** -o
+        total = total + amp * value_noise2_grid(n, period0 / 2.0 ** o, o, seed)
+        amp_sum += amp
+    return total / amp_sum
+
+
+def ridged2_grid(n: int, octaves: int, period0: float, seed: int, gain: float = 0.5):
+    """Ridged multifractal on the column centres of an n x n grid: octave o
+    contributes amp_o * (1 - |v_o|)^2 with v_o the value noise of period
+    P0 / 2^o, amp_0 = 1 and amp_o = gain^o scaled by the previous octave's
+    ridge (sharp crests, rough flanks); normalised to [-1, 1]."""
+    total = np.zeros((n, n))
+    amp_sum = 0.0
+    weight = np.ones((n, n))
+    for o in range(octaves):
+        r = (1.0 - np.abs(value_noise2_grid(n, period0 / 2.0 ** o, o, seed))) ** 2
+        amp = gain ** o
+        total = total + amp * weight * r
+        amp_sum += amp
+        weight = np.clip(r * 2.0, 0.0, 1.0)
+    return total / amp_sum * 2.0 - 1.0

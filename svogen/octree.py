@@ -322,3 +322,54 @@ def force_far(nodes: np.ndarray, every: int = 1) -> np.ndarray:
     start = idx + c24[idx]
     out[idx] = mask[idx].astype(np.uint64) | (np.uint64(FAR) << np.uint64(8)) | (start.astype(np.uint64) << np.uint64(32))
     return out
+
+
+def child_start(nodes: np.ndarray, i: int) -> int:
+    """Child-group start of interior node i (relative or far pointer)."""
+    w = int(nodes[i])
+    c24 = (w >> 8) & FAR
+    return (w >> 32) if c24 == FAR else i + c24
+
+
+def top_levels(nodes: np.ndarray, L: int):
+    """Breadth-first walk of the first L + 1 levels of a pool rooted at node
+    0 with no transformed nodes: (index, level, coord [n, 3]) of every node
+    of levels 0..L, in pool order."""
+    out_i, out_l, out_c = [], [], []
+    if nodes.shape[0] == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros((0, 3), np.int64)
+    cur = [(0, (0, 0, 0))]
+    for l in range(L + 1):
+        nxt = []
+        for i, c in cur:
+            out_i.append(i)
+            out_l.append(l)
+            out_c.append(c)
+            m = int(nodes[i]) & 0xFF
+            if m == 0 or l == L:
+                continue
+            s = child_start(nodes, i)
+            k = 0
+            for o in range(8):
+                if (m >> o) & 1:
+                    nxt.append((s + k, (2 * c[0] + (o & 1), 2 * c[1] + ((o >> 1) & 1), 2 * c[2] + ((o >> 2) & 1))))
+                    k += 1
+        cur = nxt
+    return np.asarray(out_i, np.int64), np.asarray(out_l, np.int32), np.asarray(out_c, np.int64).reshape(-1, 3)
+
+
+def mark_transformed_pool(nodes: np.ndarray, found, in_place: bool = False):
+    """mark_transformed for a pool without generation metadata: found is a
+    list of interior node indices, slot s = position in the list.  Returns
+    (nodes, slot_child, slot_node)."""
+    out = nodes if in_place else nodes.copy()
+    slot_child = np.zeros(len(found), dtype=np.uint32)
+    slot_node = np.zeros(len(found), dtype=np.int64)
+    for s, i in enumerate(found):
+        m = int(out[i]) & 0xFF
+        if m == 0:
+            raise ValueError("node %d is a leaf" % i)
+        slot_child[s] = child_start(out, int(i))
+        out[i] = np.uint64(m) | (np.uint64(XFORM_BIT | s) << np.uint64(32))
+        slot_node[s] = i
+    return out, slot_child, slot_node

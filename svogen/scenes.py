@@ -51,6 +51,12 @@ class Scene:
     def n_slots(self) -> int:
         return int(self.slot_child.shape[0])
 
+    def static_pool(self) -> np.ndarray:
+        """The static twin (every transform cleared), built on first use."""
+        if self.static_nodes is None:
+            self.static_nodes = ot.clear_transformed(self.nodes, self.slot_child)
+        return self.static_nodes
+
     def rays(self, W=None, H=None, order="tiles"):
         c = dict(self.camera)
         W = W or c["W"]
@@ -442,3 +448,72 @@ def instanced_scene(seed: int = 3, n_inst: int = 64, world_K: int = 12) -> Scene
     return Scene(name="instances4096", nodes=nodes, static_nodes=static, root=0, root_min=np.zeros(3, np.float32),
                  root_size=float(N), max_depth=20, slot_child=slot_child, slot_cell=slot_cell, slot_node=slot_node,
                  slot_parent=np.full(n_inst, NONE, np.uint32), tree=world, xform=xform, camera=camera, seed=seed)
+
+
+# ------------------------------------------------------------------ ridged terrain, depth 12
+
+def ridged_terrain_d12(seed: int = 5, frames: int = 60, n_slots: int = 256) -> Scene:
+    """Depth-12 (4096^3) heightfield h = 2048 + 2048 r, r a ridged multifractal
+    (9 octaves, P0 = 1024): about 1.5e8 nodes (1.2 GB), far beyond the MALL.
+    256 interior nodes of level 4 (256^3 cells), drawn by the seeded stream,
+    are animated by 4 keyframes each at frames {0, 20, 40, 60} + U{-5..5}:
+    a uniformly random rotation and per-axis scale 2^U[-1, 1] about the cell
+    centre, interpolated by slerp and log-linear scale (the pose of the
+    first / last keyframe holds before / after it)."""
+    from . import hfbuild
+    from .noise import ridged2_grid
+    K = 12
+    n = 1 << K
+    r = ridged2_grid(n, 9, 1024.0, seed)
+    H = np.clip(np.ceil(2048.0 + 2048.0 * r - 0.5), 0, n).astype(np.int32)
+    del r
+    nodes, _ = hfbuild.build_heightfield_pool(H, K, seed)
+    del H
+    idx, lev, crd = ot.top_levels(nodes, 4)
+    inter = (lev == 4) & ((nodes[idx] & np.uint64(0xFF)) != 0)
+    cand_i, cand_c = idx[inter], crd[inter]
+    if cand_i.shape[0] < n_slots:
+        raise RuntimeError("only %d interior level-4 nodes" % cand_i.shape[0])
+    st = Stream(seed, 13)
+    pick = []
+    seen = set()
+    while len(pick) < n_slots:
+        j = int(st.integers(1, 0, cand_i.shape[0])[0])
+        if j not in seen:
+            seen.add(j)
+            pick.append(j)
+    nodes, slot_child, slot_node = ot.mark_transformed_pool(nodes, [int(cand_i[j]) for j in pick], in_place=True)
+    size = float(1 << (K - 4))
+    slot_cell = np.zeros((n_slots, 4), np.float32)
+    centres = []
+    for s_, j in enumerate(pick):
+        slot_cell[s_, :3] = cand_c[j] * size
+        slot_cell[s_, 3] = size
+        centres.append(cand_c[j].astype(np.float64) * size + size / 2)
+    times = np.array([0, 20, 40, 60], np.float64)[None, :] + st.integers(4 * n_slots, -5, 6).reshape(n_slots, 4)
+    quats = [[xf.random_quat(st) for _ in range(4)] for _ in range(n_slots)]
+    logs = st.uniform(12 * n_slots, -1.0, 1.0).reshape(n_slots, 4, 3)
+
+    def xform(frame: int = 0):
+        f = float(frame % frames)
+        out = np.zeros((n_slots, 12), np.float32)
+        for j in range(n_slots):
+            t = times[j]
+            if f <= t[0]:
+                k, u = 0, 0.0
+            elif f >= t[3]:
+                k, u = 2, 1.0
+            else:
+                k = int(np.searchsorted(t, f, side="right")) - 1
+                k = min(max(k, 0), 2)
+                u = (f - t[k]) / (t[k + 1] - t[k])
+            q = xf.slerp(quats[j][k], quats[j][k + 1], u)
+            sc_ = 2.0 ** ((1.0 - u) * logs[j, k] + u * logs[j, k + 1])
+            out[j] = xf.to_f32(xf.about_pivot(xf.quat_to_mat(q) @ np.diag(sc_), centres[j])).reshape(12)
+        return out
+
+    camera = dict(eye=(2048.0, 5600.0, 600.0), target=(2048.0, 1200.0, 2600.0), up=(0.0, 1.0, 0.0),
+                  fov=45.0, W=3840, H=2160)
+    return Scene(name="terrain4096", nodes=nodes, static_nodes=None, root=0, root_min=np.zeros(3, np.float32),
+                 root_size=float(n), max_depth=K, slot_child=slot_child, slot_cell=slot_cell, slot_node=slot_node,
+                 slot_parent=np.full(n_slots, NONE, np.uint32), tree=None, xform=xform, camera=camera, seed=seed)

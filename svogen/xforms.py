@@ -61,3 +61,24 @@ def random_rotation(stream) -> np.ndarray:
 
 def to_f32(A) -> np.ndarray:
     return np.asarray(A, dtype=np.float64).astype(np.float32)
+
+
+def random_quat(stream) -> np.ndarray:
+    """Uniform random unit quaternion (w, x, y, z), w >= 0."""
+    q = stream.normal(4)
+    q = q / np.linalg.norm(q)
+    return q if q[0] >= 0 else -q
+
+
+def slerp(q0, q1, u: float) -> np.ndarray:
+    """Spherical linear interpolation of unit quaternions (shortest arc)."""
+    q0 = np.asarray(q0, np.float64)
+    q1 = np.asarray(q1, np.float64)
+    c = float(q0 @ q1)
+    if c < 0.0:
+        q1, c = -q1, -c
+    if c > 0.9995:
+        q = q0 + u * (q1 - q0)
+        return q / np.linalg.norm(q)
+    th = np.arccos(c)
+    return (np.sin((1.0 - u) * th) * q0 + np.sin(u * th) * q1) / np.sin(th)

@@ -15,10 +15,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 NONE = 0xFFFFFFFF
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "svo.h")).read()
+def _declared(header="svo.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(svo_[a-z_]+)\s*\(", src)))
+
+
+def test_ceiling_library_exports_every_declared_symbol():
+    from paper_1911_06001_amd import ceiling
+    L = ceiling.lib()
+    names = _declared("svo_ceiling.h")
+    assert set(names) == set(ceiling.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
 
 
 def test_library_exports_every_declared_symbol():

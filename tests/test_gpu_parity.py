@@ -353,3 +353,102 @@ def test_results_independent_of_kernel_config(ctx, torch_dev):
     finally:
         ctx.set_config(**base_cfg)
         ctx.free_scene(h)
+
+
+def _corner_rays(sc, fwd, per_slot=48, seed=0):
+    """Rays through points just inside the leaf corners nearest each moved
+    root cell's bounding sphere, in directions perpendicular to the radius:
+    each ray passes at almost exactly the sphere's radius from its centre
+    and still meets a solid leaf of that slot."""
+    import bruteforce as bf
+    rng = np.random.default_rng(seed)
+    slots, ids, C = bf.world_boxes(sc, fwd)
+    out = []
+    for s in range(sc.n_slots):
+        cell = sc.slot_cell[s].astype(np.float64)
+        Wc = bf.apply_chain(cell[:3] + cell[3] * bf.CORNERS, s, fwd, sc.slot_parent)
+        c = bf.apply_chain((cell[:3] + 0.5 * cell[3])[None], s, fwd, sc.slot_parent)[0]
+        r = np.linalg.norm(Wc - c, axis=1).max()
+        Cs = C[slots == s]
+        if Cs.shape[0] == 0:
+            continue
+        dist = np.linalg.norm(Cs - c, axis=2)                 # [k, 8]
+        far = dist.max(1)
+        for j in np.argsort(-far)[:per_slot]:
+            q = Cs[j, dist[j].argmax()]
+            p = q + 0.05 * (Cs[j].mean(0) - q)                  # just inside the leaf
+            u = rng.normal(size=3)
+            v = p - c
+            u -= v * (u @ v) / (v @ v)
+            u /= np.linalg.norm(u)
+            o = p + u * (2.0 * r)
+            out.append([o[0], o[1], o[2], 0.0, -u[0], -u[1], -u[2], np.inf])
+    return np.asarray(out, np.float32)
+
+
+@pytest.mark.parametrize("which", ["terrain_sorted", "tiny_index_order"])
+def test_sphere_cull_keeps_corner_hits(ctx, torch_dev, which):
+    """The kernel's bounding-sphere test (Eq. 4) must not cull a candidate
+    frame for rays that graze its sphere where the moved cell's corner
+    voxels touch it: at most 16 candidates take the sorted path, more take
+    the index-order path."""
+    if which == "terrain_sorted":
+        sc = S.fbm_terrain_d10()
+        fwd = sc.xform(17)
+    else:
+        sc = S.tiny_scene(7, K=6, n_slots=20, nested=False, scale_range=(1.0, 2.0))
+        fwd = sc.xform(0)
+    rays = _corner_rays(sc, fwd)
+    h = ctx.upload_scene(sc)
+    try:
+        ctx.set_transforms(h, fwd)
+        st_dev = ctx.scene_stats(h)
+        _say(which, "rays", rays.shape[0], "candidates", st_dev.n_candidates)
+        assert st_dev.n_candidates >= (17 if which == "tiny_index_order" else 4)
+        g = _trace(ctx, torch_dev, h, rays)
+    finally:
+        ctx.free_scene(h)
+    ref = oracle.trace_scene(sc, rays, fwd=fwd, margin=True)
+    st = parity.compare(g, ref, ref.margin, rays)
+    _say(which, st, "slot hits", int((ref.inst != NONE).sum()))
+    parity.assert_parity(st)
+    assert (ref.inst != NONE).mean() > 0.3
+
+
+@pytest.mark.parametrize("n_slots", [60, 150])
+def test_hierarchy_over_many_candidates(ctx, torch_dev, n_slots):
+    """More than 16 candidate frames go through the hierarchy of their world
+    boxes: camera and random rays (incl. inside starts and short tmax) equal
+    the oracle, alone, in a batch next to a sorted-path job, and in a plan."""
+    torch = torch_dev
+    sc = S.tiny_scene(11, K=7, n_slots=n_slots, nested=False, scale_range=(0.8, 2.0), translate=0.3)
+    cam_rays = S.random_rays(3, 6000, -40.0, 168.0)
+    ins = S.random_rays(4, 3000, 20.0, 108.0)
+    ins[:, 7] = np.where(np.arange(ins.shape[0]) % 3 == 0, 9.0, np.inf).astype(np.float32)
+    rays = np.concatenate([cam_rays, ins])
+    st = _check_scene(ctx, torch, sc, rays, label="hierarchy-%d" % n_slots)
+    assert st["hits"] > 0
+    h = ctx.upload_scene(sc)
+    sph = S.noisy_sphere_d6()
+    hs = ctx.upload_scene(sph)
+    try:
+        ctx.set_transforms(h, sc.xform(0))
+        ctx.set_transforms(hs, sph.xform(0))
+        assert ctx.scene_stats(h).n_candidates > 16
+        r = torch.from_numpy(rays).cuda()
+        rs = torch.from_numpy(sph.rays(W=40, H=40)[0]).cuda()
+        alone = ctx.trace(h, r)
+        jobs = [dict(scene=hs, rays=rs, **_outs(torch, rs.shape[0])), dict(scene=h, rays=r, **_outs(torch, r.shape[0]))]
+        ctx.trace_batch(jobs)
+        plan = ctx.plan([h, hs], max_jobs=4, max_frames=2 * (n_slots + 2))
+        pj = [dict(scene=hs, rays=rs, **_outs(torch, rs.shape[0])), dict(scene=h, rays=r, **_outs(torch, r.shape[0]))]
+        plan.set_jobs(pj)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.close()
+        for got in (jobs[1], pj[1]):
+            assert torch.equal(got["out_id"], alone.id) and torch.equal(got["out_t"], alone.t)
+            assert torch.equal(got["out_inst"], alone.inst) and torch.equal(got["out_normal"], alone.normal)
+    finally:
+        ctx.free_scene(h)
+        ctx.free_scene(hs)

@@ -34,15 +34,21 @@ def setup():
     ctx.close()
 
 
-def test_each_result_same_alone_and_in_the_mix(setup):
+@pytest.mark.parametrize("graph", [False, True])
+def test_each_result_same_alone_and_in_the_mix(setup, graph):
+    """Continuous batching (eager batched launches, or a captured plan
+    launch replayed per step): every request's outputs equal tracing it alone."""
     torch, ctx, entries, scenes = setup
     from paper_1911_06001_amd import serve
     reqs = serve.poisson_requests(24, 4000.0, 3, ["sphere", "terrain"],
                                   resolutions=((64, 64), (160, 90), (256, 144), (96, 200)), samples=(1, 3))
     budget = 3 * max(r.footprint for r in reqs)
-    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=60000, keep_outputs=True)
-    res = srv.run(reqs, mode="batched")
-    _say("served", serve.summarize(res), "max_used", srv.scheduler.max_used, "budget", budget)
+    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=60000, keep_outputs=True, graph=graph)
+    try:
+        res = srv.run(reqs, mode="batched")
+    finally:
+        srv.close()
+    _say("served graph=%s" % graph, serve.summarize(res), "max_used", srv.scheduler.max_used, "budget", budget)
     assert len(res) == len(reqs) and srv.scheduler.max_used <= budget
     for r in res:
         e = entries[r.req.scene]

@@ -438,3 +438,74 @@ def test_far_pointers_decode_identically(oracle_lib):
         hf = oracle.trace(far, sc.root, sc.root_min, sc.root_size, sc.slot_child, sc.slot_cell, sc.xform(0), rays)
         np.testing.assert_array_equal(hf.id, h.id)
         np.testing.assert_array_equal(hf.t, h.t)
+
+
+def _eq4_rejects(c, r, o, d, tmin, tmax):
+    """Eq. 4 (Sec. 4.1) as read for an unnormalised direction: the squared
+    distance of the ray line from the centre is l.l - (l.d)^2 / (d.d) with
+    l = c - o; a sphere is rejected when that exceeds r^2, or when its chord
+    lies wholly before tmin or after tmax."""
+    l = c - o
+    dd = (d * d).sum(-1)
+    tca = (l * d).sum(-1)
+    perp2 = np.maximum((l * l).sum(-1) - tca * tca / dd, 0.0)
+    miss = perp2 > r * r
+    half = np.sqrt(np.maximum(r * r - perp2, 0.0) / dd)
+    tc = tca / dd
+    return miss | (tc + half < tmin) | (tc - half > tmax)
+
+
+def _segment_meets(C, o, d, tmin, tmax):
+    """Exact segment vs parallelepiped (corners C [8, 3]) by clipping against
+    its six face planes."""
+    P, N = bf._faces(C[None])
+    P, N = P[0], N[0]
+    dn = d @ N.T                                   # [n, 6]
+    num = np.einsum("fk,nfk->nf", N, P[None] - o[:, None, :])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tt = num / dn
+    tn = np.where(dn < 0, tt, -np.inf).max(1)
+    tf = np.where(dn > 0, tt, np.inf).min(1)
+    par_out = ((dn == 0) & (num < 0)).any(1)
+    return ~par_out & (np.maximum(tn, tmin) <= np.minimum(tf, tmax))
+
+
+def test_p7_eq4_sphere_never_drops_a_hit():
+    """P7: the bounding-sphere cull (centre = image of the cell centre,
+    radius = distance to the farthest image corner) never rejects a ray
+    segment that meets the moved cell, over random affine maps (rotation,
+    anisotropic scale, shear, translation) and random rays, many of them
+    aimed at the cell's corners.  The other reading of the centre (the map's
+    translation, i.e. the image of the cell's origin corner) does drop hits."""
+    rng = np.random.default_rng(17)
+    hits = rejected = dropped_other = 0
+    for trial in range(300):
+        A = rng.normal(size=(3, 3)) * rng.uniform(0.3, 3.0, size=3)
+        if abs(np.linalg.det(A)) < 1e-2:
+            continue
+        b = rng.uniform(-50, 50, 3)
+        lo = rng.uniform(-8, 8, 3)
+        size = rng.uniform(0.5, 16)
+        C = (lo + size * bf.CORNERS) @ A.T + b
+        c = (lo + 0.5 * size) @ A.T + b
+        r = np.linalg.norm(C - c, axis=1).max()
+        n = 256
+        # half aimed at points near the corners (inside the cell), half random
+        k = rng.integers(0, 8, n)
+        w = rng.uniform(0.0, 0.05, (n, 1))
+        target = C[k] * (1 - w) + c * w
+        rand = rng.uniform(-2, 2, (n, 3)) * r + c
+        target[n // 2:] = rand[n // 2:]
+        d = rng.normal(size=(n, 3)) * rng.uniform(0.1, 10.0, (n, 1))
+        back = rng.uniform(0.1, 4.0, (n, 1)) * r / np.linalg.norm(d, axis=1, keepdims=True)
+        o = target - back * d
+        tmin = np.where(rng.random(n) < 0.3, rng.uniform(0, 2, n) * back[:, 0], 0.0)
+        tmax = np.where(rng.random(n) < 0.3, rng.uniform(0, 3, n) * back[:, 0], np.inf)
+        meet = _segment_meets(C, o, d, tmin, tmax)
+        rej = _eq4_rejects(c, r, o, d, tmin, tmax)
+        assert not (meet & rej).any(), trial
+        hits += int(meet.sum())
+        rejected += int(rej.sum())
+        dropped_other += int((meet & _eq4_rejects(b + lo @ A.T, r, o, d, tmin, tmax)).sum())
+    assert hits > 10000 and rejected > 10000     # neither side of the test is vacuous
+    assert dropped_other > 0

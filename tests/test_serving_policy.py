@@ -44,7 +44,7 @@ def _sim(reqs, budget, max_rays, finish_after=2, seed=0, policy="fair", max_jobs
     return s, order, done, covered
 
 
-@pytest.mark.parametrize("policy", ["fifo", "fair"])
+@pytest.mark.parametrize("policy", ["fifo", "fair", "edf"])
 def test_budget_fifo_and_exact_coverage(policy):
     reqs = poisson_requests(60, 1000.0, 4, ["a", "b"], resolutions=((16, 16), (40, 30), (64, 48)), samples=(1, 3))
     budget = max(r.footprint for r in reqs) * 3
@@ -86,3 +86,21 @@ def test_fair_share_lets_small_requests_through():
         chunks = s.plan(active)
         got_small = any(a.req.rid == 1 for a, _, _ in chunks)
         assert got_small == small_first_step, policy
+
+
+def test_edf_orders_by_deadline():
+    """edf: deadline = arrival + slack * rays / ref_rate.  A small request
+    that arrives shortly after a large one goes first; a large request whose
+    deadline has come is not passed by small work that arrived later."""
+    big = Request(0, 0.0, "a", 0, 2000, 1000, 2)          # 4e6 rays: deadline 3 ms at 4e9 rays/s, slack 3
+    small = Request(1, 0.0005, "a", 0, 64, 64, 1)         # deadline 0.5 ms + 3 us
+    late = Request(2, 0.004, "a", 0, 64, 64, 1)           # arrives after the big one's deadline
+    s = Scheduler(10**12, max_rays=5000, policy="edf")
+    active = []
+    adm = lambda r: active.append(_Active(r, Result(r), None, {}, None)) or active[-1]
+    s.admit(collections.deque([big, small]), adm)
+    first = s.plan(active)
+    assert first[0][0].req.rid == 1                       # the small request first
+    s.admit(collections.deque([late]), adm)
+    nxt = s.plan(active)
+    assert nxt[0][0].req.rid == 0                         # the big request is not passed again
