@@ -141,6 +141,70 @@ def instances_throughput(ctx, steps):
     return res
 
 
+def c5_throughput(ctx, steps, frames=60):
+    """Depth-12 ridged terrain (4096^3, ~1.5e8 nodes = 1.2 GB pool, 256
+    animated level-4 subtrees): per frame, upload that frame's transforms,
+    trace 3840x2160 primary rays, generate 2 cosine-weighted AO rays per
+    pixel on the device and trace them.  Kernel times from HIP events on the
+    launch stream; algorithmic bytes per ray from the oracle's counters on a
+    sample of the same rays (every 997th)."""
+    import torch
+    import oracle
+    from svogen import scenes
+    t0 = time.perf_counter()
+    sc = scenes.ridged_terrain_d12(frames=frames)
+    log("depth-12 terrain: %d nodes (%.1f s)" % (sc.nodes.shape[0], time.perf_counter() - t0))
+    h = ctx.upload_scene(sc)
+    rays_np, _ = sc.rays()
+    n = rays_np.shape[0]
+    rays = torch.from_numpy(rays_np).cuda()
+    xf = [sc.xform(f) for f in range(frames)]
+    ctx.set_transforms(h, xf[0])
+    tuned = ctx.tune(h, rays).as_dict()
+    stream = torch.cuda.current_stream()
+    prim = ctx.trace(h, rays)
+    ao = ctx.ao_rays(rays, prim, k=2, seed=5, radius=64.0)
+    out_ao = ctx.trace(h, ao)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    w0 = time.perf_counter()
+    for k in range(steps):
+        e = ev[k]
+        ctx.set_transforms(h, xf[k % frames], stream=stream)
+        e[0].record(stream)
+        ctx.trace_into(h, rays, prim.id, prim.t, prim.inst, prim.normal, stream=stream)
+        e[1].record(stream)
+        ctx.ao_rays(rays, prim, k=2, seed=5 + k, radius=64.0, out=ao, stream=stream)
+        e[2].record(stream)
+        ctx.trace_into(h, ao, out_ao.id, out_ao.t, out_ao.inst, out_ao.normal, stream=stream)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) / steps
+    pm = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    am = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
+    # algorithmic bytes of the primary trace from the oracle on a sample
+    idx = np.arange(0, n, 997)
+    hs = oracle.trace_scene(sc, rays_np[idx], frame=0, counters=True)
+    bpr = float((8.0 * hs.nnode.astype(np.float64) + 64.0 * hs.nframe + 32.0 + 24.0).mean())
+    achieved = bpr * n / (pm * 1e-3) / 1e9
+    st = ctx.scene_stats(h)
+    ctx.free_scene(h)
+    res = {"workload": "terrain4096: depth-12 (4096^3) ridged-fBm heightfield SVO, %d nodes (%.2f GB), 256 level-4 "
+                       "subtrees animated by 4 jittered keyframes (slerp + log-scale lerp), 3840x2160 primary + 2 "
+                       "AO rays per pixel" % (sc.nodes.shape[0], sc.nodes.nbytes / 1e9),
+           "nodes": int(sc.nodes.shape[0]), "pool_bytes": int(sc.nodes.nbytes), "candidates": int(st.n_candidates),
+           "inline": int(st.n_inline), "kernel": tuned, "steps": steps,
+           "primary": {"rays": n, "kernel_ms": round(pm, 4), "mrays_per_s": round(n / pm / 1e3, 2)},
+           "ao": {"rays": 2 * n, "kernel_ms": round(am, 4), "mrays_per_s": round(2 * n / am / 1e3, 2)},
+           "frame_ms_wall": round(wall * 1e3, 4),
+           "roofline_primary": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_ray": round(bpr, 2),
+                                "sample_rays": int(idx.shape[0])}}
+    log("depth-12 terrain: primary %.0f Mrays/s, AO %.0f Mrays/s, %.2f ms/frame" % (
+        res["primary"]["mrays_per_s"], res["ao"]["mrays_per_s"], res["frame_ms_wall"]))
+    return res
+
+
 def serve_latency(ctx, terrain, terrain_handle, n_requests, loads, warm=100):
     """p50/p99 frame latency of Poisson request streams over the noisy-sphere
     and terrain scenes (resolutions 256^2 .. 2048x1152, 1-5 rays per pixel)
@@ -204,6 +268,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--no-instances", action="store_true", help="skip the instanced-scene measurement")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the gather / stream ceiling kernels")
+    ap.add_argument("--no-c5", action="store_true", help="skip the depth-12 terrain measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -342,6 +407,9 @@ def main():
     instances = None
     if not args.no_instances:
         instances = instances_throughput(ctx, max(5, K // 6))
+    c5 = None
+    if not args.no_c5:
+        c5 = c5_throughput(ctx, max(5, K // 6))
     serving = None
     if args.serve_requests > 0:
         serving = serve_latency(ctx, sc, anim, args.serve_requests, [float(x) for x in args.serve_loads.split(",")])
@@ -373,6 +441,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "instances": instances,
+        "terrain4096": c5,
     }
     ctx.free_scene(anim)
     ctx.free_scene(stat)

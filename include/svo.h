@@ -116,12 +116,15 @@ typedef struct {
 /* Kernel configuration; svo_tune() picks one, svo_set_config() sets one.
    Zero fields select the library defaults. */
 typedef struct {
-    uint32_t waves_per_block;   /* 1..8 wavefronts (64 lanes) per work-group */
-    uint32_t blocks_per_cu;     /* resident work-groups per compute unit for the persistent grid */
+    uint32_t waves_per_block;   /* 1..16 wavefronts (64 lanes) per work-group */
+    uint32_t blocks_per_cu;     /* work-groups per compute unit of the persistent grid (capped by what LDS and 32 waves per CU let reside) */
     uint32_t lds_cache_nodes;   /* first N pool nodes (the top levels, breadth-first) kept in LDS */
     uint32_t refill_lanes;      /* 0 or 64: a wave takes 64-ray tiles; 1..63: claim new rays once that many lanes are idle */
     uint32_t step_limit;        /* node steps per ray before SVO_STEP_LIMIT */
-    uint32_t reserved[3];
+    uint32_t sync_lanes;        /* 0 or 64: a wave's lanes leave the walk loop together once all wait; 1..63: once that
+                                   many lanes wait (a hit, a frame change, or no ray), the others pausing mid-walk */
+    uint32_t claim_tiles;       /* 64-ray tiles a wave takes from the work queue at once (0: 2; at most 64) */
+    uint32_t reserved[1];
 } svo_config;
 
 /* ABI version the library was built with (SVO_ABI_VERSION). */
@@ -278,8 +281,8 @@ int svo_get_config(svo_ctx* ctx, svo_config* cfg);
 int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
 
 /* Autotuner.  Times candidate kernel configurations (waves per work-group,
-   resident work-groups per CU, LDS pool-prefix size, lane refill) on n
-   device sample rays against `scene` under its current transforms, keeps
+   resident work-groups per CU, LDS pool-prefix size, lane refill, tiles per
+   work-queue claim) on n device sample rays against `scene` under its current transforms, keeps
    the fastest for that scene -- later svo_trace_rays calls on it use it, and
    a batch uses it when that scene holds most of the batch's rays -- and
    writes it to *best (nullable).  Results never depend on the

@@ -87,9 +87,15 @@ def measure(pool_bytes: int, blocks: int, threads: int, hbm_bytes: int = 4 << 30
     sink = torch.empty(max(blocks * threads, sblocks * sthreads), dtype=torch.int64, device=dev)
     out = {"grid": [blocks, threads], "pool_bytes": int(n_words * 8)}
 
-    loads_ind, chains_ind = 64, 8
-    t = _time(lambda: gather(pool, blocks, threads, chains_ind, loads_ind, False, 1, sink), reps)
-    out["gather_independent_GBps"] = round(blocks * threads * chains_ind * loads_ind * 8 / t / 1e9, 1)
+    # independent gathers: the best over loads in flight per thread (too
+    # many outstanding misses thrash the memory system)
+    loads_ind = 64
+    per_chain = {}
+    for chains in (1, 2, 4, 8):
+        t = _time(lambda: gather(pool, blocks, threads, chains, loads_ind, False, 1, sink), reps)
+        per_chain[chains] = round(blocks * threads * chains * loads_ind * 8 / t / 1e9, 1)
+    out["gather_independent_by_chains_GBps"] = per_chain
+    out["gather_independent_GBps"] = max(per_chain.values())
     loads_dep = 256
     t = _time(lambda: gather(pool, blocks, threads, 1, loads_dep, True, 2, sink), reps)
     out["gather_dependent_GBps"] = round(blocks * threads * loads_dep * 8 / t / 1e9, 1)

@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <numeric>
 #include <set>
 #include <string>
 #include <vector>
@@ -310,11 +311,12 @@ struct Scene {
 struct svo_ctx {
     int device = 0;
     int n_cu = 0;
-    size_t max_lds = 0;
+    size_t max_lds = 0;       // LDS one work-group may use
+    size_t lds_per_cu = 0;    // LDS of one compute unit
     svo_config cfg{};
     uint32_t next_scene = 1;
     std::map<uint32_t, std::unique_ptr<Scene>> scenes;
-    uint32_t* d_queue = nullptr;                // kMaxStreams pairs of counters
+    uint32_t* d_queue = nullptr;                // kMaxStreams work queues of kQueueWords
     std::map<hipStream_t, uint32_t> stream_slot;
     // ring of batch tables (job records, frames, candidates): pinned staging
     // + device copy, reused once the launch that read them has finished
@@ -364,19 +366,23 @@ namespace {
 
 svo_config default_config() {
     svo_config c{};
-    c.waves_per_block = 4;
-    c.blocks_per_cu = 4;
+    c.waves_per_block = 8;
+    c.blocks_per_cu = 2;
     c.lds_cache_nodes = 1024;
-    c.refill_lanes = 0;
+    c.refill_lanes = 48;
     c.step_limit = 1u << 20;
+    c.sync_lanes = 64;
+    c.claim_tiles = 2;
     return c;
 }
 
 int check_config(const svo_config& c) {
-    if (c.waves_per_block < 1 || c.waves_per_block > 8) return fail(SVO_EINVAL, "waves_per_block must be 1..8");
+    if (c.waves_per_block < 1 || c.waves_per_block > 16) return fail(SVO_EINVAL, "waves_per_block must be 1..16");
     if (c.blocks_per_cu < 1 || c.blocks_per_cu > 32) return fail(SVO_EINVAL, "blocks_per_cu must be 1..32");
     if (c.lds_cache_nodes > 16384) return fail(SVO_EINVAL, "lds_cache_nodes must be <= 16384");
     if (c.step_limit < 1) return fail(SVO_EINVAL, "step_limit must be >= 1");
+    if (c.sync_lanes > 64) return fail(SVO_EINVAL, "sync_lanes must be <= 64");
+    if (c.claim_tiles > 64) return fail(SVO_EINVAL, "claim_tiles must be <= 64");
     return SVO_OK;
 }
 
@@ -696,10 +702,15 @@ int svo_create(svo_ctx** out, int device_ordinal) {
     int lds = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device_ordinal));
     c->max_lds = (size_t)lds;
+    int lds_cu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device_ordinal) != hipSuccess ||
+        lds_cu <= 0)
+        lds_cu = lds;
+    c->lds_per_cu = (size_t)std::max(lds_cu, lds);
     c->cfg = default_config();
     HIP_TRY(svo::prepare_trace(c->max_lds));
-    HIP_TRY(hipMalloc((void**)&c->d_queue, kMaxStreams * 2 * sizeof(uint32_t)));
-    HIP_TRY(hipMemset(c->d_queue, 0, kMaxStreams * 2 * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc((void**)&c->d_queue, kMaxStreams * svo::kQueueWords * sizeof(uint32_t)));
+    HIP_TRY(hipMemset(c->d_queue, 0, kMaxStreams * svo::kQueueWords * sizeof(uint32_t)));
     HIP_TRY(hipDeviceSynchronize());
     *out = c.release();
     return SVO_OK;
@@ -902,8 +913,28 @@ int queue_slot(svo_ctx* ctx, hipStream_t st, uint32_t& qslot) {
     return SVO_OK;
 }
 
+// Work-groups of the persistent grid per CU: the configured count, capped by
+// what can be resident at once (LDS per CU, 32 waves per CU), so that no
+// work-group waits for another to exit before it starts.
+uint32_t resident_blocks(const svo_ctx* ctx, const svo_config& c, size_t lds) {
+    uint32_t b = c.blocks_per_cu;
+    if (lds) b = std::min<uint32_t>(b, (uint32_t)(ctx->lds_per_cu / lds));
+    b = std::min<uint32_t>(b, 32u / c.waves_per_block);
+    return std::max<uint32_t>(b, 1u);
+}
+
+// A stride coprime with `tiles` near tiles / golden ratio: consecutive claims
+// land far apart in the image.
+uint64_t tile_stride(uint64_t tiles) {
+    if (tiles <= 2) return 1;
+    uint64_t s = (uint64_t)((double)tiles * 0.6180339887498949) | 1ull;
+    while (s > 1 && std::gcd(s, tiles) != 1) s -= 2;
+    return s ? s : 1;
+}
+
 // Size LDS (shrinking the node cache if needed) and launch.
 int launch(svo_ctx* ctx, const svo_config& c, svo::TraceArgs& a, hipStream_t st) {
+    a.tile_stride = tile_stride((a.n_rays + 63) / 64);
     size_t lds = svo::trace_lds_bytes(a, c.waves_per_block);
     while (lds > ctx->max_lds && a.lds_nodes > 0) {
         a.lds_nodes = (a.lds_nodes / 2) & ~1u;
@@ -915,7 +946,7 @@ int launch(svo_ctx* ctx, const svo_config& c, svo::TraceArgs& a, hipStream_t st)
     L.waves_per_block = c.waves_per_block;
     const uint64_t tiles = (a.n_rays + 63) / 64;
     const uint64_t want = (tiles + c.waves_per_block - 1) / c.waves_per_block;
-    const uint64_t cap = (uint64_t)ctx->n_cu * c.blocks_per_cu;
+    const uint64_t cap = (uint64_t)ctx->n_cu * resident_blocks(ctx, c, lds);
     L.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
     L.lds_bytes = lds;
     const hipError_t e = svo::launch_trace(a, L, st);
@@ -925,6 +956,8 @@ int launch(svo_ctx* ctx, const svo_config& c, svo::TraceArgs& a, hipStream_t st)
 
 void fill_common(const svo_config& c, svo::TraceArgs& a) {
     a.refill = (c.refill_lanes == 0 || c.refill_lanes > 64) ? 64u : c.refill_lanes;
+    a.claim = 64u * ((c.claim_tiles == 0) ? 2u : c.claim_tiles);
+    a.sync = (c.sync_lanes == 0 || c.sync_lanes > 64) ? 64u : c.sync_lanes;
     a.step_limit = c.step_limit;
 }
 
@@ -1000,9 +1033,10 @@ int pack_jobs(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, const std::set
     return SVO_OK;
 }
 
-// Write job records, frame records, candidates (absolute frame indices) and
-// spheres of a packing into host memory; the jobs of the cached pool get
-// `cache_nodes` LDS nodes.
+// Write job records, frame records, candidates (absolute frame indices),
+// spheres and hierarchy nodes (skipped when br is null: launches that take
+// every candidate through the sorted path) of a packing into host memory;
+// the jobs of the cached pool get `cache_nodes` LDS nodes.
 void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t* cr, float* sr, svo::BvhNode* br,
                   uint32_t cache_nodes) {
     uint64_t begin = 0;
@@ -1014,7 +1048,8 @@ void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t
         std::memcpy(sr + 4 * (size_t)Q.frame_base, tab + sphere_offset(S.n_frames, S.n_slots), (size_t)S.n_frames * 16);
         const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + cand_offset(S.n_frames));
         for (uint32_t c = 0; c < Q.T.n_cand; ++c) cr[Q.cand_base + c] = Q.frame_base + sc[c];
-        std::memcpy(br + Q.bvh_base, tab + bvh_offset(S.n_frames, S.n_slots), (size_t)Q.T.n_bvh * sizeof(svo::BvhNode));
+        if (br)
+            std::memcpy(br + Q.bvh_base, tab + bvh_offset(S.n_frames, S.n_slots), (size_t)Q.T.n_bvh * sizeof(svo::BvhNode));
         const svo_job& J = *Q.j;
         jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
                             J.out_normal, begin, Q.frame_base, Q.cand_base, Q.T.n_cand,
@@ -1067,7 +1102,8 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + cand_offset(S->n_frames));
     a.spheres = reinterpret_cast<const float4*>(S->d_table[S->cur] + sphere_offset(S->n_frames, S->n_slots));
     a.bvh = reinterpret_cast<const svo::BvhNode*>(S->d_table[S->cur] + bvh_offset(S->n_frames, S->n_slots));
-    a.n_bvh_total = S->n_bvh;
+    // the hierarchy is walked only past kMaxSortedCand candidates
+    a.n_bvh_total = S->n_cand > svo::kMaxSortedCand ? S->n_bvh : 0u;
     a.bvh_depth = S->bvh_depth;
     a.n_jobs = 1;
     a.n_frames = S->n_frames;
@@ -1075,7 +1111,7 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     a.max_cand = S->n_cand;
     a.n_rays = n;
     a.cache_src = S->d_nodes;
-    a.queue = ctx->d_queue + 2 * qslot;
+    a.queue = ctx->d_queue + svo::kQueueWords * qslot;
     a.lds_nodes = cache;
     a.stack_levels = S->stack_levels;
     a.nest_levels = S->nest_levels;
@@ -1116,7 +1152,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         const size_t bb = sb + (size_t)P.frames * 16;
         const size_t bytes = bb + (size_t)P.bvh * sizeof(svo::BvhNode);
         svo::TraceArgs a{};
-        a.n_bvh_total = P.bvh;
+        a.n_bvh_total = P.max_cand > svo::kMaxSortedCand ? P.bvh : 0u;
         a.bvh_depth = P.bvh_depth;
         a.n_jobs = (uint32_t)P.jobs.size();
         a.n_frames = P.frames;
@@ -1124,7 +1160,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         a.max_cand = P.max_cand;
         a.n_rays = P.total;
         a.cache_src = P.cache_src;
-        a.queue = ctx->d_queue + 2 * qslot;
+        a.queue = ctx->d_queue + svo::kQueueWords * qslot;
         a.lds_nodes = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, cache_pool_nodes) & ~1u;
         a.sort_cand = P.max_cand <= svo::kMaxSortedCand ? 1u : 0u;
         a.stack_levels = P.stack_levels;
@@ -1207,7 +1243,7 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         pl->off_cand = pl->off_frames + (size_t)pl->max_frames * sizeof(svo::FrameRec);
         pl->off_sph = (pl->off_cand + (size_t)pl->max_frames * sizeof(uint32_t) + 15) & ~(size_t)15;
         pl->off_bvh = pl->off_sph + (size_t)pl->max_frames * 16;
-        pl->max_bvh = 2 * pl->max_frames;
+        pl->max_bvh = pl->max_cand > svo::kMaxSortedCand ? 2 * pl->max_frames : 0u;
         pl->bvh_depth_cap = bvh_levels(pl->max_cand);
         pl->bytes = pl->off_bvh + (size_t)pl->max_bvh * sizeof(svo::BvhNode);
 
@@ -1231,19 +1267,19 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         }
         if (lds > ctx->max_lds) return fail(SVO_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
         pl->launch_cfg.waves_per_block = pl->cfg.waves_per_block;
-        pl->launch_cfg.blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ctx->n_cu * pl->cfg.blocks_per_cu);
+        pl->launch_cfg.blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ctx->n_cu * resident_blocks(ctx, pl->cfg, lds));
         pl->launch_cfg.lds_bytes = lds;
 
         HIP_TRY(hipSetDevice(ctx->device));
         auto release = [&]() { destroy_plan(*pl); };
         if (hipMalloc((void**)&pl->dev, pl->bytes) != hipSuccess ||
             hipHostMalloc((void**)&pl->host, pl->bytes, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&pl->d_queue, 2 * sizeof(uint32_t)) != hipSuccess) {
+            hipMalloc((void**)&pl->d_queue, svo::kQueueWords * sizeof(uint32_t)) != hipSuccess) {
             release();
             return fail(SVO_ENOMEM, "plan allocation failed");
         }
         std::memset(pl->host, 0, pl->bytes);
-        if (hipMemset(pl->d_queue, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+        if (hipMemset(pl->d_queue, 0, svo::kQueueWords * sizeof(uint32_t)) != hipSuccess ||
             hipMemcpy(pl->dev, pl->host, pl->bytes, hipMemcpyHostToDevice) != hipSuccess ||
             hipEventCreateWithFlags(&pl->ev, hipEventDisableTiming) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess) {
@@ -1277,7 +1313,7 @@ int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_
         if (P.frames > plan->max_frames)
             return fail(SVO_ERANGE, "%u frame records, the plan holds %u", P.frames, plan->max_frames);
         if (P.stack_levels > plan->stack_cap || P.nest_levels > plan->nest_cap || P.max_cand > plan->max_cand ||
-            P.bvh > plan->max_bvh || P.bvh_depth > plan->bvh_depth_cap)
+            (plan->max_bvh && P.bvh > plan->max_bvh) || P.bvh_depth > plan->bvh_depth_cap)
             return fail(SVO_ERANGE, "jobs exceed the plan's stack, nesting or candidate capacity");
         if (plan->ev_pending) {
             HIP_TRY(hipSetDevice(ctx->device));
@@ -1287,10 +1323,11 @@ int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_
         unsigned char* H = plan->host;
         svo::LaunchHdr hdr{};
         hdr.n_rays = P.total;
+        hdr.tile_stride = tile_stride((P.total + 63) / 64);
         hdr.n_jobs = (uint32_t)P.jobs.size();
         hdr.n_frames = P.frames;
         hdr.n_cand_total = P.cands;
-        hdr.n_bvh_total = P.bvh;
+        hdr.n_bvh_total = plan->max_bvh ? P.bvh : 0u;
         uint32_t fill = 0;
         for (auto& J : P.jobs)
             if (J.S->d_nodes == P.cache_src) fill = (uint32_t)std::min<uint64_t>(plan->args.lds_nodes, J.S->n_nodes) & ~1u;
@@ -1299,7 +1336,7 @@ int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_
         std::memcpy(H, &hdr, sizeof hdr);
         write_tables(P, reinterpret_cast<svo::JobRec*>(H + plan->off_jobs), reinterpret_cast<svo::FrameRec*>(H + plan->off_frames),
                      reinterpret_cast<uint32_t*>(H + plan->off_cand), reinterpret_cast<float*>(H + plan->off_sph),
-                     reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh), fill);
+                     plan->max_bvh ? reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh) : nullptr, fill);
         return SVO_OK;
     } catch (const std::bad_alloc&) {
         return fail(SVO_ENOMEM, "out of host memory");
@@ -1362,41 +1399,52 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     const svo_config was_cfg = S->cfg;
     svo_config win = base;
     float win_ms = 1e30f;
-    static const uint32_t kWaves[] = {2, 4, 8};
+    static const uint32_t kWaves[] = {4, 8, 16};
     static const uint32_t kBlocks[] = {1, 2, 3, 4, 6, 8};
-    static const uint32_t kCache[] = {0, 1024, 4096};
+    static const uint32_t kCache[] = {1024, 4096};
     static const uint32_t kRefill[] = {0, 48};
-    int rc = SVO_OK;
+    static const uint32_t kClaim[] = {1, 2, 4};
+    std::vector<svo_config> cands;
     for (uint32_t w : kWaves)
         for (uint32_t b : kBlocks) {
             if (w * b > 32) continue;  // resident waves per CU
             for (uint32_t c : kCache)
-                for (uint32_t r : kRefill) {
-                    svo_config cand = base;
-                    cand.waves_per_block = w;
-                    cand.blocks_per_cu = b;
-                    cand.lds_cache_nodes = c;
-                    cand.refill_lanes = r;
-                    S->tuned = true;
-                    S->cfg = cand;
-                    rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
-                    if (rc == SVO_ERANGE) continue;  // does not fit in LDS
-                    if (rc) break;
-                    HIP_TRY(hipEventRecord(e0, st));
-                    for (int k = 0; k < 3 && rc == SVO_OK; ++k)
-                        rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
-                    if (rc) break;
-                    HIP_TRY(hipEventRecord(e1, st));
-                    HIP_TRY(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < win_ms) {
-                        win_ms = ms;
-                        win = cand;
+                for (uint32_t r : kRefill)
+                    for (uint32_t y : kClaim) {
+                        svo_config cand = base;
+                        cand.waves_per_block = w;
+                        cand.blocks_per_cu = b;
+                        cand.lds_cache_nodes = c;
+                        cand.refill_lanes = r;
+                        cand.claim_tiles = y;
+                        cands.push_back(cand);
                     }
-                }
-            if (rc && rc != SVO_ERANGE) break;
         }
+    int rc = SVO_OK;
+    for (const svo_config& cand : cands) {
+        S->tuned = true;
+        S->cfg = cand;
+        rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
+        if (rc == SVO_ERANGE) continue;  // does not fit in LDS
+        if (rc) break;
+        if (hipEventRecord(e0, st) != hipSuccess) {
+            rc = fail(SVO_EDEVICE, "tuner event record failed");
+            break;
+        }
+        for (int k = 0; k < 3 && rc == SVO_OK; ++k)
+            rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(SVO_EDEVICE, "tuner timing failed");
+            break;
+        }
+        if (ms < win_ms) {
+            win_ms = ms;
+            win = cand;
+        }
+    }
     cleanup();
     if (rc && rc != SVO_ERANGE) {
         S->tuned = was_tuned;

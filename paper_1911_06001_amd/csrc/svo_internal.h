@@ -71,24 +71,38 @@ static_assert(sizeof(JobRec) == 80, "job record must be 80 bytes");
 
 constexpr uint32_t kMaxJobs = 256;
 
+// Work queue of one launch: kQueueParts claim counters, each on its own
+// 128-byte line, then a bitmap of exhausted partitions, then the
+// finished-work-group counter.  Claims are interleaved over the partitions
+// (claim slot s belongs to partition s mod kQueueParts) so that no single
+// address serialises them; a wave starts on its own partition, and a wave
+// that finds a partition dry marks it in the bitmap and moves on to the next
+// partition the bitmap still shows as open.
+constexpr uint32_t kQueueParts = 64;
+constexpr uint32_t kQueueStride = 32;                              // uint32 words between counters
+constexpr uint32_t kQueueDry = kQueueParts * kQueueStride;         // 2 words: bitmap of dry partitions
+constexpr uint32_t kQueueFinished = kQueueDry + kQueueStride;      // finished work-groups
+constexpr uint32_t kQueueWords = kQueueFinished + kQueueStride;
+
 // Launch-wide counts of a plan launch, read by the kernel from the head of
 // the plan's device table: a captured launch keeps its arguments across
 // replays, so whatever changes between replays lives in device memory.
 struct alignas(16) LaunchHdr {
     uint64_t n_rays;              // all jobs
     const uint64_t* cache_src;    // pool whose prefix is cached in LDS (nullptr: none)
+    uint64_t tile_stride;         // as TraceArgs::tile_stride, for n_rays
     uint32_t n_jobs;              // <= TraceArgs::n_jobs (the capacity)
     uint32_t n_frames;            // <= TraceArgs::n_frames
     uint32_t n_cand_total;        // <= TraceArgs::n_cand_total
     uint32_t lds_nodes;           // <= TraceArgs::lds_nodes, even
     uint32_t n_bvh_total;         // <= TraceArgs::n_bvh_total
-    uint32_t pad[7];
+    uint32_t pad[5];
 };
 static_assert(sizeof(LaunchHdr) == 64, "launch header must be 64 bytes");
 
 // In a plan launch (hdr != nullptr) n_jobs, n_frames, n_cand_total,
 // n_bvh_total and lds_nodes are capacities that size the LDS layout, and the header holds
-// the counts; n_rays and cache_src are ignored.
+// the counts; n_rays, tile_stride and cache_src are ignored.
 struct TraceArgs {
     const LaunchHdr* hdr;     // plan launches: counts in device memory; else nullptr
     const JobRec* jobs;       // device job table, or nullptr: the single job in job0
@@ -105,12 +119,15 @@ struct TraceArgs {
     uint32_t max_cand;        // largest per-job candidate count
     uint64_t n_rays;          // all jobs
     const uint64_t* cache_src;  // pool whose prefix is cached in LDS
-    uint32_t* queue;          // [0] rays claimed, [1] finished work-groups
+    uint32_t* queue;          // kQueueWords: partition counters, then finished work-groups
     uint32_t lds_nodes;       // pool prefix cached in LDS (even)
     uint32_t stack_levels;    // traversal stack entries per lane
     uint32_t nest_levels;     // frame stack entries per lane (inline frames)
     uint32_t sort_cand;       // 1: candidates in entry order via a per-lane LDS table
     uint32_t refill;          // a wave claims new rays once this many lanes are idle (1..64)
+    uint32_t claim;           // rays a wave takes from a partition counter at once (a multiple of 64)
+    uint64_t tile_stride;     // claim i covers tile (i * tile_stride) mod tiles (coprime: a permutation)
+    uint32_t sync;            // waiting lanes (events or idle) at which a wave leaves the walk loop (1..64)
     uint32_t step_limit;
 };
 

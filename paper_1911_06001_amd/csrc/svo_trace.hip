@@ -10,7 +10,8 @@
 //   3. walk the frame's octree front to back, top-down (the role of the
 //      parametric traversal in the paper, Sec. 5): integer cell corners, a
 //      per-level LDS stack of (child start, mask), and an exit by the highest
-//      changed coordinate bit, so popping needs no search;
+//      changed coordinate bit, so popping needs no search (5 bytes per
+//      level and lane: a 32-bit child start and an 8-bit mask);
 //   4. at a transformed node whose moved content stays inside its static
 //      cell, switch into that node's frame in place (Sec. 3, Fig. 1: the ray,
 //      not the model, is transformed) and resume the enclosing walk after it;
@@ -22,9 +23,15 @@
 //   6. write id, slot, t and the normal (entry face, inverse transpose).
 //
 // Work distribution: a persistent grid.  Each wave keeps 64 rays in flight
-// and claims new ones from a global counter once `refill` lanes are idle (64
-// = whole tiles).  The last work-group to finish resets the counter so the
-// next launch on the stream starts from zero.
+// and refills lanes once `refill` of them are idle (64 = whole tiles), from
+// a range of `claim` rays it takes at once from one of kQueueParts counters
+// (claims interleaved over the counters, each wave starting on its own), so
+// that no single address serialises the claims.  Claims visit
+// the 64-ray tiles in a stride permutation, so that expensive regions of an
+// image (rays grazing a surface) spread over time and over waves instead of
+// reaching a few waves back to back.  The last
+// work-group to finish resets the counters so the next launch on the stream
+// starts from zero.
 #include <hip/hip_runtime.h>
 
 #include "svo_internal.h"
@@ -160,11 +167,11 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
     const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 80 +
                           align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec) +
                           (size_t)a.n_bvh_total * sizeof(BvhNode);
-    const size_t per_wave = cand_lane_bytes(a) * 64 + (size_t)a.stack_levels * 64 * 8 + (size_t)a.nest_levels * 64 * 16;
+    const size_t per_wave = cand_lane_bytes(a) * 64 + (size_t)a.stack_levels * 64 * 5 + (size_t)a.nest_levels * 64 * 16;
     return shared + per_wave * waves_per_block;
 }
 
-__global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
+__global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* p = smem;
     uint64_t* lds_nodes = reinterpret_cast<uint64_t*>(p);
@@ -182,13 +189,15 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     const size_t ent_bytes = cand_lane_bytes(a) * 64;
-    const size_t per_wave = ent_bytes + (size_t)a.stack_levels * 64 * 8 + (size_t)a.nest_levels * 64 * 16;
+    const size_t per_wave = ent_bytes + (size_t)a.stack_levels * 64 * 5 + (size_t)a.nest_levels * 64 * 16;
     const uint32_t bst_cap = a.bvh_depth + 1;
     unsigned char* wp = p + per_wave * wave;
     float* ent = reinterpret_cast<float*>(wp) + lane;                                   // candidate c at ent[c * 64]
     uint2* bst = reinterpret_cast<uint2*>(wp) + lane;                                   // hierarchy entry k at bst[k * 64]
-    uint2* stk = reinterpret_cast<uint2*>(wp + ent_bytes) + lane;                       // level l at stk[l * 64]
-    uint4* fst = reinterpret_cast<uint4*>(wp + ent_bytes + (size_t)a.stack_levels * 512) + lane;  // nest n at fst[n * 64]
+    // traversal stack, level l: child start at stkc[l * 64], child mask at stkm[l * 64]
+    uint32_t* stkc = reinterpret_cast<uint32_t*>(wp + ent_bytes) + lane;
+    uint8_t* stkm = reinterpret_cast<uint8_t*>(wp + ent_bytes + (size_t)a.stack_levels * 256) + lane;
+    uint4* fst = reinterpret_cast<uint4*>(wp + ent_bytes + (size_t)a.stack_levels * 320) + lane;  // nest n at fst[n * 64]
 
     // launch-wide counts: the arguments, or a plan's header (capacities
     // above bound them, so every LDS copy below stays in its region)
@@ -196,9 +205,11 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     uint32_t n_jobs = a.n_jobs, n_frames = a.n_frames, n_cand_total = a.n_cand_total, fill_nodes = a.lds_nodes;
     uint32_t n_bvh = a.n_bvh_total;
     const uint64_t* cache_src = a.cache_src;
+    uint64_t tstride = a.tile_stride;
     if (a.hdr) {
         const LaunchHdr& h = *a.hdr;
         n_rays = h.n_rays;
+        tstride = h.tile_stride;
         n_jobs = min(h.n_jobs, a.n_jobs);
         n_frames = min(h.n_frames, a.n_frames);
         n_cand_total = min(h.n_cand_total, a.n_cand_total);
@@ -231,6 +242,14 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     __syncthreads();
 
     const uint32_t refill = a.refill;
+    const uint32_t claim = a.claim;
+    const uint32_t sync = a.sync;
+    // partition-local ray indices run to part_len (whole tiles); a wave owns
+    // the claimed range [rlo, rhi) of partition q (wave-uniform state)
+    const uint64_t n_tiles = (n_rays + 63) >> 6;
+    const uint32_t part_len = (uint32_t)((n_tiles + kQueueParts - 1) / kQueueParts) * 64u;
+    uint32_t q = (blockIdx.x * (blockDim.x >> 6) + wave) % kQueueParts, rlo = 0, rhi = 0;
+    uint64_t known_dry = 0;  // partitions this wave knows to be dry
 
     // per-lane state
     uint32_t mode = M_DONE;
@@ -325,14 +344,49 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
         if (exhausted && nidle == 64u) break;
         if (!exhausted && nidle >= refill) {
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)idle) - 1u;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&a.queue[0], nidle);
-            base = __shfl(base, (int)leader);
-            if ((uint64_t)base + nidle >= n_rays) exhausted = true;
+            if (rlo >= rhi) {
+                // claim the next range of partition q.  A dry partition is
+                // marked in the shared bitmap by the first wave to overflow
+                // it, so a set bit always means dry (an unset one may be
+                // stale); the wave moves on to the next partition it does not
+                // know to be dry, and is done once it knows all of them are.
+                uint32_t base = part_len;
+                while (known_dry != ~0ull) {
+                    uint32_t* ctr = a.queue + q * kQueueStride;
+                    if (lane == leader) base = atomicAdd(ctr, claim);
+                    base = __shfl(base, (int)leader);
+                    if (base < part_len) break;
+                    uint64_t dry = 0;
+                    if (lane == leader) {
+                        uint32_t* bm = a.queue + kQueueDry;
+                        if (base < part_len + claim) atomicOr(bm + (q >> 5), 1u << (q & 31u));   // first to overflow
+                        dry = (uint64_t)__hip_atomic_load(bm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                              ((uint64_t)__hip_atomic_load(bm + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32);
+                    }
+                    known_dry |= __shfl(dry, (int)leader) | (1ull << q);
+                    if (known_dry == ~0ull) break;
+                    // the next partition after q not known to be dry, cyclically
+                    const uint64_t open = ~known_dry;
+                    const uint64_t above = open & ~((2ull << q) - 1ull);
+                    q = (uint32_t)__ffsll((unsigned long long)(above ? above : open)) - 1u;
+                }
+                if (known_dry == ~0ull) {
+                    exhausted = true;
+                } else {
+                    rlo = base;
+                    rhi = min(base + claim, part_len);
+                }
+            }
+            const uint32_t take = (rlo < rhi) ? min(nidle, rhi - rlo) : 0u;
+            const uint32_t first = rlo;
+            rlo += take;
             if (mode == M_DONE) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-                const uint64_t gidx = (uint64_t)base + rank;
+                const uint32_t j = first + rank;
+                const uint64_t slot = (uint64_t)(j >> 6) * kQueueParts + q;     // claim order
+                uint64_t gidx = n_rays;
+                if (rank < take && slot < n_tiles) gidx = ((slot * tstride) % n_tiles) * 64u + (j & 63u);
                 if (gidx < n_rays) {
                     // the job holding this launch-wide ray index (jobs are in ray order)
                     uint32_t lo = 0, hi = n_jobs;
@@ -416,9 +470,8 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                 pz = nz & keep;
                 const uint32_t nlvl = fr.K - h;
                 if (nlvl < lvl) {
-                    const uint2 e = stk[(sbase + nlvl) * 64];
-                    pchild = e.x;
-                    pmask = e.y;
+                    pchild = stkc[(sbase + nlvl) * 64];
+                    pmask = stkm[(sbase + nlvl) * 64];
                 }
                 lvl = nlvl;
                 size = nsize;
@@ -437,56 +490,71 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
                 ev = advance(ex, ey, ez, min3f(ex, ey, ez));
             }
-            // the hot loop: visit, descend or advance until something happens
-            while (ev == EV_NONE) {
-                if (++steps > a.step_limit) {
-                    ev = EV_LIMIT;
-                    break;
+            // the hot loop: visit, descend or advance until something happens.
+            // A lane with an event stops walking; the wave leaves the loop
+            // together once `sync` lanes wait (events, or not walking), and
+            // lanes still mid-walk pause there and resume on the next pass.
+            for (;;) {
+                if (ev == EV_NONE) {
+                    if (++steps > a.step_limit) {
+                        ev = EV_LIMIT;
+                    } else {
+                        const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
+                        const float ey = fmaf((float)(py + size), fr.iy, fr.by);
+                        const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
+                        const float tc1 = min3f(ex, ey, ez);
+                        const uint32_t oct =
+                            (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
+                        bool adv = true;
+                        if ((pmask >> oct) & 1u) {
+                            const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
+                            // the child's corner does not depend on the node:
+                            // computed while its load is in flight
+                            const uint32_t hs = size >> 1;
+                            const uint32_t cx = px + ((fmaf((float)(px + hs), fr.ix, fr.bx) <= tc0) ? hs : 0u);
+                            const uint32_t cy = py + ((fmaf((float)(py + hs), fr.iy, fr.by) <= tc0) ? hs : 0u);
+                            const uint32_t cz = pz + ((fmaf((float)(pz + hs), fr.iz, fr.bz) <= tc0) ? hs : 0u);
+                            // separate LDS and global reads (a select between the two
+                            // would become one generic load waiting on both counters)
+                            uint64_t wl = 0, wg = 0;
+                            if (n_lds) wl = lds_nodes[min(cidx, n_lds - 1u)];
+                            if (cidx >= n_lds) wg = gld(nodes, cidx);
+                            const uint64_t w = (cidx < n_lds) ? wl : wg;
+                            const uint32_t w0 = (uint32_t)w;
+                            const uint32_t w1 = (uint32_t)(w >> 32);
+                            const uint32_t cm = w0 & 0xFFu;
+                            if (cm == 0u) {
+                                ev = EV_HIT;
+                                hit_id = cidx;
+                                adv = false;
+                            } else if (!(w1 & kXform)) {
+                                stkc[(sbase + lvl) * 64] = pchild;
+                                stkm[(sbase + lvl) * 64] = (uint8_t)pmask;
+                                const uint32_t c24 = w0 >> 8;
+                                pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
+                                pmask = cm;
+                                ++lvl;
+                                size = hs;
+                                px = cx;
+                                py = cy;
+                                pz = cz;
+                                adv = false;
+                            } else {
+                                const uint32_t f = fbase + 1u + (w1 & 0x7FFFFFFFu);
+                                if (lds_frames[f].info & FR_INLINE) {
+                                    ev = EV_ENTER;
+                                    xf = f;
+                                    xf_tc1 = tc1;
+                                    adv = false;
+                                }
+                                // else a candidate frame: traced on its own, empty here
+                            }
+                        }
+                        if (adv) ev = advance(ex, ey, ez, tc1);
+                    }
                 }
-                const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
-                const float ey = fmaf((float)(py + size), fr.iy, fr.by);
-                const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
-                const float tc1 = min3f(ex, ey, ez);
-                const uint32_t oct =
-                    (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
-                if ((pmask >> oct) & 1u) {
-                    const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
-                    // separate LDS and global reads (a select between the two
-                    // would become one generic load waiting on both counters)
-                    uint64_t wl = 0, wg = 0;
-                    if (n_lds) wl = lds_nodes[min(cidx, n_lds - 1u)];
-                    if (cidx >= n_lds) wg = gld(nodes, cidx);
-                    const uint64_t w = (cidx < n_lds) ? wl : wg;
-                    const uint32_t w0 = (uint32_t)w;
-                    const uint32_t w1 = (uint32_t)(w >> 32);
-                    const uint32_t cm = w0 & 0xFFu;
-                    if (cm == 0u) {
-                        ev = EV_HIT;
-                        hit_id = cidx;
-                        break;
-                    }
-                    if (!(w1 & kXform)) {
-                        stk[(sbase + lvl) * 64] = make_uint2(pchild, pmask);
-                        const uint32_t c24 = w0 >> 8;
-                        pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
-                        pmask = cm;
-                        ++lvl;
-                        size >>= 1;
-                        px += (fmaf((float)(px + size), fr.ix, fr.bx) <= tc0) ? size : 0u;
-                        py += (fmaf((float)(py + size), fr.iy, fr.by) <= tc0) ? size : 0u;
-                        pz += (fmaf((float)(pz + size), fr.iz, fr.bz) <= tc0) ? size : 0u;
-                        continue;
-                    }
-                    const uint32_t f = fbase + 1u + (w1 & 0x7FFFFFFFu);
-                    if (lds_frames[f].info & FR_INLINE) {
-                        ev = EV_ENTER;
-                        xf = f;
-                        xf_tc1 = tc1;
-                        break;
-                    }
-                    // a candidate frame: traced on its own, empty here
-                }
-                ev = advance(ex, ey, ez, tc1);
+                const uint64_t busy = __ballot(ev == EV_NONE);
+                if (busy == 0ull || 64u - (uint32_t)__popcll(busy) >= sync) break;
             }
             if (ev == EV_HIT) {
                 // the first solid leaf front to back ends this top-level frame
@@ -503,7 +571,8 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                 int ea;
                 if (frame_setup(C, r, fminf(tl, xf_tc1), cfr, t0, ea)) {
                     // save where the enclosing walk stands, then enter in place
-                    stk[(sbase + lvl) * 64] = make_uint2(pchild, pmask);
+                    stkc[(sbase + lvl) * 64] = pchild;
+                    stkm[(sbase + lvl) * 64] = (uint8_t)pmask;
                     fst[nest * 64] = make_uint4(cur_f | (lvl << 11) | (sbase << 16) | ((uint32_t)eaxis << 23), px, py, pz);
                     ++nest;
                     sbase += lvl;
@@ -521,7 +590,7 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                 } else {
                     resume = true;  // missed it: the cell is empty for this ray
                 }
-            } else {  // EV_END
+            } else if (ev == EV_END) {
                 if (nest > 0) {
                     // back to the enclosing frame, just past the transformed cell
                     --nest;
@@ -537,9 +606,8 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
                     int ea;
                     frame_setup(lds_frames[cur_f], r, tl, fr, t0, ea);
                     size = 1u << (fr.K - lvl);
-                    const uint2 sv = stk[(sbase + lvl) * 64];
-                    pchild = sv.x;
-                    pmask = sv.y;
+                    pchild = stkc[(sbase + lvl) * 64];
+                    pmask = stkm[(sbase + lvl) * 64];
                     resume = true;
                 } else {
                     mode = M_SELECT;
@@ -621,10 +689,13 @@ __global__ __launch_bounds__(512) void trace_kernel(TraceArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        const uint32_t prev = atomicAdd(&a.queue[1], 1u);
+        uint32_t* fin = a.queue + kQueueFinished;
+        const uint32_t prev = atomicAdd(fin, 1u);
         if (prev == gridDim.x - 1) {
-            atomicExch(&a.queue[0], 0u);
-            atomicExch(&a.queue[1], 0u);
+            for (uint32_t p = 0; p < kQueueParts; ++p) atomicExch(a.queue + p * kQueueStride, 0u);
+            atomicExch(a.queue + kQueueDry, 0u);
+            atomicExch(a.queue + kQueueDry + 1, 0u);
+            atomicExch(fin, 0u);
         }
     }
 }

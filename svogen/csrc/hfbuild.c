@@ -113,7 +113,8 @@ static inline uint64_t pack(uint32_t x, uint32_t y, uint32_t z, int k) {
  * level_count[l] receives the nodes of level l (l = 0..K).  Returns the
  * node count, -1 on bad arguments or allocation failure, -2 when `cap` is
  * too small. */
-static int64_t walk(int K, const int32_t* H, int64_t seed, uint64_t* nodes, int64_t cap, int64_t* level_count) {
+static int64_t walk(int K, const int32_t* H, int64_t seed, uint64_t* nodes, int64_t cap, int64_t* level_count,
+                    uint64_t far_from) {
     if (K < 0 || K > 16 || !H) return -1;
     Pyr p;
     if (pyr_build(&p, K, H)) {
@@ -176,7 +177,7 @@ static int64_t walk(int K, const int32_t* H, int64_t seed, uint64_t* nodes, int6
             if (nodes) {
                 if (idx >= cap) { rc = -2; break; }
                 const uint64_t off = (uint64_t)(start - idx);
-                if (off >= FAR)
+                if (off >= far_from)
                     nodes[idx] = (uint64_t)mask | (FAR << 8) | ((uint64_t)start << 32);
                 else
                     nodes[idx] = (uint64_t)mask | (off << 8);
@@ -195,10 +196,13 @@ static int64_t walk(int K, const int32_t* H, int64_t seed, uint64_t* nodes, int6
 }
 
 int64_t svogen_hf_count(int K, const int32_t* H, int64_t* level_count) {
-    return walk(K, H, 0, NULL, 0, level_count);
+    return walk(K, H, 0, NULL, 0, level_count, FAR);
 }
 
-int64_t svogen_hf_build(int K, const int32_t* H, int64_t seed, uint64_t* nodes, int64_t cap, int64_t* level_count) {
-    if (!nodes) return -1;
-    return walk(K, H, seed, nodes, cap, level_count);
+/* far_from: child offsets of at least this many nodes become far pointers
+ * (FAR, i.e. 2^24 - 1, for the pool format; smaller values only for tests) */
+int64_t svogen_hf_build(int K, const int32_t* H, int64_t seed, uint64_t* nodes, int64_t cap, int64_t* level_count,
+                        int64_t far_from) {
+    if (!nodes || far_from < 1 || far_from > (int64_t)FAR) return -1;
+    return walk(K, H, seed, nodes, cap, level_count, (uint64_t)far_from);
 }

@@ -33,13 +33,17 @@ def lib():
         L.svogen_hf_count.restype = I64
         L.svogen_hf_count.argtypes = [ctypes.c_int, P, P]
         L.svogen_hf_build.restype = I64
-        L.svogen_hf_build.argtypes = [ctypes.c_int, P, I64, P, I64, P]
+        L.svogen_hf_build.argtypes = [ctypes.c_int, P, I64, P, I64, P, I64]
         _lib = L
     return _lib
 
 
-def build_heightfield_pool(H: np.ndarray, K: int, seed: int):
-    """(nodes uint64 [n], nodes per level int64 [K + 1]) for columns H[x, z]."""
+FAR = 0xFFFFFF
+
+
+def build_heightfield_pool(H: np.ndarray, K: int, seed: int, far_from: int = FAR):
+    """(nodes uint64 [n], nodes per level int64 [K + 1]) for columns H[x, z].
+    far_from < 2^24 - 1 writes far pointers for smaller offsets too (tests)."""
     n = 1 << K
     Hc = np.ascontiguousarray(np.asarray(H).reshape(n, n), np.int32)
     counts = np.zeros(K + 1, np.int64)
@@ -49,7 +53,7 @@ def build_heightfield_pool(H: np.ndarray, K: int, seed: int):
         raise RuntimeError("heightfield pool: bad arguments or out of memory")
     nodes = np.empty(total, np.uint64)
     if total:
-        got = lib().svogen_hf_build(K, P(Hc), int(seed), P(nodes), total, P(counts))
+        got = lib().svogen_hf_build(K, P(Hc), int(seed), P(nodes), total, P(counts), int(far_from))
         if got != total:
             raise RuntimeError("heightfield pool build failed (%d)" % got)
     return nodes, counts

@@ -1,0 +1,75 @@
+"""Depth-12 ridged terrain (4096^3, ~1.5e8 nodes = 1.2 GB pool, 256 animated
+level-4 subtrees, candidates through the box hierarchy): full 3840x2160
+launches of primary rays and 2 AO rays per pixel, checked against the oracle
+on sampled rays (every 997th ray plus one whole 64x64 tile) of two
+animation frames (needs the GPU)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+from svogen import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-c5]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1911_06001_amd import svo
+    _say("building the depth-12 terrain")
+    sc = S.ridged_terrain_d12()
+    _say("nodes", sc.nodes.shape[0])
+    ctx = svo.Context(0)
+    h = ctx.upload_scene(sc)
+    rays_np, _ = sc.rays()
+    yield torch, svo, ctx, sc, h, rays_np
+    ctx.free_scene(h)
+    ctx.close()
+
+
+def _sample(n, W=3840):
+    every = np.arange(0, n, 997)
+    tile = np.arange(64) + 64 * 5000          # a whole 8x8-pixel tile ... 64 consecutive rays
+    return np.unique(np.concatenate([every, tile]))
+
+
+@pytest.mark.parametrize("frame", [0, 29])
+def test_primary_and_ao_sampled(env, frame):
+    torch, svo, ctx, sc, h, rays_np = env
+    fwd = sc.xform(frame)
+    ctx.set_transforms(h, fwd)
+    st = ctx.scene_stats(h)
+    _say("frame", frame, "candidates", st.n_candidates, "inline", st.n_inline)
+    assert st.n_candidates > 16                 # the hierarchy path
+    r = torch.from_numpy(rays_np).cuda()
+    prim = ctx.trace(h, r)
+    ao = ctx.ao_rays(r, prim, k=2, seed=5, radius=64.0)
+    out = ctx.trace(h, ao)
+    torch.cuda.synchronize()
+    n = rays_np.shape[0]
+    idx = _sample(n)
+    g = parity.to_numpy(prim)
+    got = tuple(x[idx] for x in g)
+    ref = oracle.trace_scene(sc, rays_np[idx], fwd=fwd, margin=True)
+    stp = parity.compare(got, ref, ref.margin, rays_np[idx])
+    _say("primary", stp, "slot hits", int((ref.inst != 0xFFFFFFFF).sum()))
+    parity.assert_parity(stp, 1e-3 if idx.shape[0] < 10000 else 1e-4)
+    assert (ref.id != 0xFFFFFFFF).mean() > 0.5
+    # AO rays of the same sample's pixels (2 per pixel, consecutive)
+    aidx = np.stack([2 * idx, 2 * idx + 1], 1).reshape(-1)
+    a = ao[torch.from_numpy(aidx).cuda()].cpu().numpy()
+    ga = parity.to_numpy(out)
+    gota = tuple(x[aidx] for x in ga)
+    refa = oracle.trace_scene(sc, a, fwd=fwd, margin=True)
+    sta = parity.compare(gota, refa, refa.margin, a)
+    _say("ao", sta, "occluded", float((refa.id != 0xFFFFFFFF).mean()))
+    parity.assert_parity(sta, 1e-3)
