@@ -262,6 +262,7 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-cache-nodes", type=int, default=-1)
     ap.add_argument("--refill", type=int, default=-1)
+    ap.add_argument("--claim-tiles", type=int, default=0)
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests per offered load in the served-latency runs (0 disables)")
     ap.add_argument("--serve-loads", default="0.3,0.6,0.9", help="offered loads, fractions of saturation")
@@ -316,6 +317,8 @@ def main():
         knobs["lds_cache_nodes"] = args.lds_cache_nodes
     if args.refill >= 0:
         knobs["refill_lanes"] = args.refill
+    if args.claim_tiles:
+        knobs["claim_tiles"] = args.claim_tiles
     cfg = ctx.set_config(**knobs).as_dict()
     log("kernel config", cfg)
     anim = ctx.upload_scene(sc)

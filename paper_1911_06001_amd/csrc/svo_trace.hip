@@ -219,6 +219,17 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
         if (!cache_src) fill_nodes = 0;
         if (n_jobs == 0) n_rays = 0;
     }
+    // work-groups beyond what this launch's rays need (a plan's grid is
+    // fixed) fill no LDS and claim nothing
+    const uint32_t wpb = blockDim.x >> 6;
+    const bool active = (uint64_t)blockIdx.x < (((n_rays + 63) >> 6) + wpb - 1) / wpb;
+    if (!active) {
+        fill_nodes = 0;
+        n_frames = 0;
+        n_cand_total = 0;
+        n_bvh = 0;
+        n_jobs = 0;
+    }
     for (uint32_t i = threadIdx.x; i < fill_nodes; i += blockDim.x) lds_nodes[i] = cache_src[i];
     {
         const uint4* src = reinterpret_cast<const uint4*>(a.frames);
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
     // the claimed range [rlo, rhi) of partition q (wave-uniform state)
     const uint64_t n_tiles = (n_rays + 63) >> 6;
     const uint32_t part_len = (uint32_t)((n_tiles + kQueueParts - 1) / kQueueParts) * 64u;
-    uint32_t q = (blockIdx.x * (blockDim.x >> 6) + wave) % kQueueParts, rlo = 0, rhi = 0;
+    uint32_t q = (blockIdx.x * wpb + wave) % kQueueParts, rlo = 0, rhi = 0;
     uint64_t known_dry = 0;  // partitions this wave knows to be dry
 
     // per-lane state
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
     float tc0 = 0.f;
     int eaxis = 3;
     bool resume = false;
-    bool exhausted = false;  // wave-uniform
+    bool exhausted = !active;  // wave-uniform
 
     auto record_hit = [&](float t, uint32_t id, uint32_t f, int axis) {
         const uint32_t inst = lds_frames[f].inst;

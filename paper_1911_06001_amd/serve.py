@@ -177,7 +177,7 @@ def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: 
 class Server:
     def __init__(self, ctx: svo.Context, scenes: Dict[str, SceneEntry], hbm_budget: int,
                  max_rays_per_step: int = 1 << 22, inflight_steps: int = 2, keep_outputs: bool = False,
-                 policy: str = "edf", graph: bool = False, max_jobs: int = 32, max_frames: int = 160):
+                 policy: str = "edf", graph: bool = False, max_jobs: int = 16, max_frames: int = 64):
         import torch
         self.torch = torch
         self.ctx = ctx
