@@ -194,6 +194,26 @@ int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint3
 int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                    uint32_t* out_inst, float* out_t, float* out_normal, void* stream);
 
+/* Trace with the hit buffer of the previous frame (Sec. 4.3, applied to
+   transforms on nodes): on entry the outputs hold the results of an
+   earlier svo_trace_rays / svo_trace_rays_reuse of the same rays against
+   the same scene, under any transforms; on return they hold the results
+   under the current transforms, identical to svo_trace_rays.  A ray whose
+   previous result is a hit in the static world frame (inst == SVO_NONE) or
+   a miss keeps it unchanged when no moved frame -- a transformed subtree
+   entered in place or traced as a candidate -- can lie in front of it (the
+   ray's entry into its moved root cell, after its bounding sphere and the
+   candidate hierarchy's boxes, tested up to the previous hit with the
+   current transforms); every other ray is traced
+   again.  The static world never changes, so this is exact.  out_inst is
+   required (it is read); out_normal may be NULL only if it was NULL before.
+   retraced: nullable device uint64 to which the number of rays traced again
+   is added (the caller zeroes it).  The caller guarantees the rays and
+   outputs are those of the earlier trace; anything else gives undefined
+   (but in-bounds) results.  Errors as for svo_trace_rays. */
+int svo_trace_rays_reuse(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                         uint32_t* out_inst, float* out_t, float* out_normal, uint64_t* retraced, void* stream);
+
 /* One job of a batched launch: rays traced against one scene under one set
    of transforms. */
 typedef struct {

@@ -526,6 +526,7 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
     }
     std::vector<Aff> world(S.n_slots);
     std::vector<uint32_t> depth(S.n_slots, 0), sbase(S.n_slots, 0);
+    std::vector<uint32_t> inline_frames;
     for (uint32_t s : A.order) {
         const int32_t p = A.slot_parent[s];
         world[s] = aff_mul(p < 0 ? aff_identity() : world[p], fwd[s]);
@@ -594,6 +595,7 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
             sbase[s] = (parent_inline ? sbase[p] : 0) + A.slot_level[s];
             T.nest_levels = std::max(T.nest_levels, d);
             T.stack_levels = std::max(T.stack_levels, sbase[s] + K + 1);
+            inline_frames.push_back(1 + s);
             ++T.n_inline;
         } else {
             cand[T.n_cand++] = 1 + s;
@@ -601,6 +603,9 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
         }
     }
     if (T.stack_levels > 127) return fail(SVO_ERANGE, "nested frames need %u stack levels (limit 127)", T.stack_levels);
+    // the in-place frames follow the candidates in the list (the hit-buffer
+    // test of svo_trace_rays_reuse checks every moved frame)
+    for (uint32_t i = 0; i < T.n_inline; ++i) cand[T.n_cand + i] = inline_frames[i];
     // hierarchy over the candidates' world boxes (the image of each moved
     // root cell), leaves in candidate-list order
     if (T.n_cand) {
@@ -1011,9 +1016,10 @@ int pack_jobs(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, const std::set
             Q.T.nest_levels = S->nest_levels;
             Q.T.n_bvh = S->n_bvh;
             Q.T.bvh_depth = S->bvh_depth;
+            Q.T.n_inline = S->n_inline;
         }
         P.frames += S->n_frames;
-        P.cands += Q.T.n_cand;
+        P.cands += Q.T.n_cand + Q.T.n_inline;
         P.bvh += Q.T.n_bvh;
         P.bvh_depth = std::max(P.bvh_depth, Q.T.bvh_depth);
         P.total += J.n;
@@ -1047,13 +1053,13 @@ void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t
         std::memcpy(fr + Q.frame_base, tab, (size_t)S.n_frames * sizeof(svo::FrameRec));
         std::memcpy(sr + 4 * (size_t)Q.frame_base, tab + sphere_offset(S.n_frames, S.n_slots), (size_t)S.n_frames * 16);
         const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + cand_offset(S.n_frames));
-        for (uint32_t c = 0; c < Q.T.n_cand; ++c) cr[Q.cand_base + c] = Q.frame_base + sc[c];
+        for (uint32_t c = 0; c < Q.T.n_cand + Q.T.n_inline; ++c) cr[Q.cand_base + c] = Q.frame_base + sc[c];
         if (br)
             std::memcpy(br + Q.bvh_base, tab + bvh_offset(S.n_frames, S.n_slots), (size_t)Q.T.n_bvh * sizeof(svo::BvhNode));
         const svo_job& J = *Q.j;
         jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
                             J.out_normal, begin, Q.frame_base, Q.cand_base, Q.T.n_cand,
-                            S.d_nodes == P.cache_src ? cache_nodes : 0u, Q.bvh_base};
+                            S.d_nodes == P.cache_src ? cache_nodes : 0u, Q.bvh_base, Q.T.n_inline};
         begin += J.n;
     }
 }
@@ -1078,8 +1084,12 @@ uint32_t stack_bound(const Scene& S) {
 
 extern "C" {
 
-int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
-                   uint32_t* out_inst, float* out_t, float* out_normal, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id, uint32_t* out_inst,
+               float* out_t, float* out_normal, void* stream, bool reuse, unsigned long long* retraced) {
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     Scene* S = find_scene(ctx, scene);
     if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
@@ -1097,7 +1107,7 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     const uint32_t cache = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, S->n_nodes) & ~1u;
     a.jobs = nullptr;
     a.job0 = svo::JobRec{S->d_nodes, reinterpret_cast<const float4*>(rays), out_id, out_inst, out_t, out_normal,
-                         0, 0, 0, S->n_cand, cache, 0};
+                         0, 0, 0, S->n_cand, cache, 0, S->n_inline};
     a.frames = reinterpret_cast<const svo::FrameRec*>(S->d_table[S->cur]);
     a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + cand_offset(S->n_frames));
     a.spheres = reinterpret_cast<const float4*>(S->d_table[S->cur] + sphere_offset(S->n_frames, S->n_slots));
@@ -1107,7 +1117,7 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     a.bvh_depth = S->bvh_depth;
     a.n_jobs = 1;
     a.n_frames = S->n_frames;
-    a.n_cand_total = S->n_cand;
+    a.n_cand_total = S->n_cand + S->n_inline;
     a.max_cand = S->n_cand;
     a.n_rays = n;
     a.cache_src = S->d_nodes;
@@ -1117,7 +1127,25 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     a.nest_levels = S->nest_levels;
     a.sort_cand = S->n_cand <= svo::kMaxSortedCand ? 1u : 0u;
     fill_common(cfg, a);
+    a.reuse = reuse ? 1u : 0u;
+    a.retraced = retraced;
     return launch(ctx, cfg, a, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                   uint32_t* out_inst, float* out_t, float* out_normal, void* stream) {
+    return trace_rays(ctx, scene, rays, n, out_id, out_inst, out_t, out_normal, stream, false, nullptr);
+}
+
+int svo_trace_rays_reuse(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                         uint32_t* out_inst, float* out_t, float* out_normal, uint64_t* retraced, void* stream) {
+    if (n && !out_inst) return fail(SVO_EINVAL, "out_inst is required to reuse previous hits");
+    return trace_rays(ctx, scene, rays, n, out_id, out_inst, out_t, out_normal, stream, true,
+                      reinterpret_cast<unsigned long long*>(retraced));
 }
 
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {

@@ -66,6 +66,7 @@ struct alignas(16) JobRec {
     uint32_t n_cand;
     uint32_t lds_nodes;       // pool prefix of this job's scene held in LDS (0: none)
     uint32_t bvh_base;        // the job's hierarchy root in the launch's node array
+    uint32_t n_inline;        // in-place frames, listed after the job's candidates
 };
 static_assert(sizeof(JobRec) == 80, "job record must be 80 bytes");
 
@@ -126,6 +127,8 @@ struct TraceArgs {
     uint32_t sort_cand;       // 1: candidates in entry order via a per-lane LDS table
     uint32_t refill;          // a wave claims new rays once this many lanes are idle (1..64)
     uint32_t claim;           // rays a wave takes from a partition counter at once (a multiple of 64)
+    uint32_t reuse;           // 1: the outputs hold the previous trace of these rays (hit buffer)
+    unsigned long long* retraced;  // reuse: rays traced again are added here (nullable)
     uint64_t tile_stride;     // claim i covers tile (i * tile_stride) mod tiles (coprime: a permutation)
     uint32_t sync;            // waiting lanes (events or idle) at which a wave leaves the walk loop (1..64)
     uint32_t step_limit;

@@ -321,6 +321,60 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
         return true;
     };
 
+    // Hit buffer (Sec. 4.3, for transforms on nodes): the outputs hold the
+    // previous trace of this ray.  A previous hit in the static world frame
+    // (or a miss) is still the answer unless some moved frame -- in place or
+    // candidate -- now lies in front of it; the world frame itself never
+    // changes.  Every moved frame (through the candidate hierarchy's boxes
+    // when there is one) is tested up to the previous hit.
+    auto previous_stands = [&]() -> bool {
+        // a moved frame can hold a hit no later than tlim only if the ray
+        // enters its root cell by then: the sphere first, then the exact
+        // root-cell entry the walk itself uses (leaf entries never precede it)
+        auto may_reach = [&](uint32_t f, float tlim) -> bool {
+            if (!sphere_may_hit(lds_sph[f], r, tlim)) return false;
+            FrameRay cfr;
+            float t0;
+            int ea;
+            return frame_setup(lds_frames[f], r, tlim, cfr, t0, ea);
+        };
+        const JobRec& J = lds_jobs[job];
+        if (!J.out_inst) return false;
+        const uint32_t pid = gld(J.out_id, ri);
+        const uint32_t pinst = gld(J.out_inst, ri);
+        const float pt = gld(J.out_t, ri);
+        if (pinst != kNone || pid == kStepLimitId || isnan(pt)) return false;
+        const float tlim = fminf(pt, r.tmax);
+        const uint32_t nin = J.n_inline;
+        for (uint32_t i = 0; i < nin; ++i)
+            if (may_reach(lds_cand[cbase + ncand + i], tlim)) return false;
+        if (ncand == 0) return true;
+        if (a.sort_cand) {
+            for (uint32_t c = 0; c < ncand; ++c)
+                if (may_reach(lds_cand[cbase + c], tlim)) return false;
+            return true;
+        }
+        // any candidate box in front of the previous hit?
+        const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
+        const float ix = 1.0f / (fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
+        const float iy = 1.0f / (fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
+        const float iz = 1.0f / (fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
+        uint32_t sp = 0;
+        if (box_entry(lds_bvh[bbase], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(0u, 0u);
+        while (sp > 0u) {
+            const BvhNode& N = lds_bvh[bbase + bst[(--sp) * 64].x];
+            if (N.b & kBvhLeaf) {
+                for (uint32_t c = N.a; c < N.a + (N.b & 0xFFFFu); ++c)
+                    if (may_reach(lds_cand[cbase + c], tlim)) return false;
+                continue;
+            }
+            if (sp + 2u > bst_cap) return false;   // cannot happen (depth bound); trace it then
+            if (box_entry(lds_bvh[bbase + N.a], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(N.a, 0u);
+            if (box_entry(lds_bvh[bbase + N.b], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(N.b, 0u);
+        }
+        return true;
+    };
+
     auto finish = [&]() {
         float nx = 0.f, ny = 0.f, nz = 0.f;
         if (best_id == kStepLimitId) {
@@ -355,6 +409,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
         if (exhausted && nidle == 64u) break;
         if (!exhausted && nidle >= refill) {
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)idle) - 1u;
+            bool retrace = false;
             if (rlo >= rhi) {
                 // claim the next range of partition q.  A dry partition is
                 // marked in the shared bitmap by the first wave to overflow
@@ -427,9 +482,14 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     bsp = 0;
                     leaf_i = 0;
                     leaf_end = 0;
-                    if (!ray_valid(r)) {
+                    bool keep = false;
+                    if (a.reuse && ray_valid(r)) keep = previous_stands();
+                    if (keep) {
+                        // the previous result stands: nothing to trace or write
+                    } else if (!ray_valid(r)) {
                         finish();
                     } else {
+                        retrace = true;
                         tl = r.tmax;
                         if (a.sort_cand) {
                             for (uint32_t c = 0; c < ncand; ++c) {
@@ -458,6 +518,10 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                         mode = start_frame(fbase) ? M_WALK : M_SELECT;
                     }
                 }
+            }
+            if (a.reuse && a.retraced) {
+                const uint64_t re = __ballot(retrace);
+                if (lane == leader && re) atomicAdd(a.retraced, (unsigned long long)__popcll(re));
             }
         }
 

@@ -28,7 +28,7 @@ MAX_INLINE_NEST = 4
 EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
            "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
-           "svo_generate_ao_rays", "svo_plan_create", "svo_plan_set_jobs", "svo_plan_launch", "svo_plan_destroy")
+           "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_plan_create", "svo_plan_set_jobs", "svo_plan_launch", "svo_plan_destroy")
 
 
 class SvoError(RuntimeError):
@@ -120,6 +120,7 @@ def lib():
         "svo_set_transforms": (I, [P, U32, U32, U32, P, P]),
         "svo_trace_rays": (I, [P, U32, P, U64, P, P, P, P, P]),
         "svo_trace_batch": (I, [P, ctypes.POINTER(Job), U32, P]),
+        "svo_trace_rays_reuse": (I, [P, U32, P, U64, P, P, P, P, P, P]),
         "svo_tune": (I, [P, U32, P, U64, P, ctypes.POINTER(Config)]),
         "svo_generate_primary_rays": (I, [P, ctypes.POINTER(Camera), P, P]),
         "svo_generate_ao_rays": (I, [P, P, P, P, U64, U32, U32, ctypes.c_float, ctypes.c_float, P, P]),
@@ -336,6 +337,17 @@ class Context:
                                           int(seed) & 0xFFFFFFFF, float(radius), float(offset), out.data_ptr(),
                                           _stream_handle(stream)))
         return out
+
+    def trace_reuse(self, scene: int, rays, hits: "Hits", retraced=None, stream=None):
+        """Update `hits` (the previous trace of these rays on this scene) for
+        the scene's current transforms, retracing only rays that can change.
+        retraced: optional int64 device tensor [1] the retraced count is added to."""
+        _check(lib().svo_trace_rays_reuse(self._ptr, int(scene), rays.data_ptr(), rays.shape[0], hits.id.data_ptr(),
+                                          hits.inst.data_ptr(), hits.t.data_ptr(),
+                                          hits.normal.data_ptr() if hits.normal is not None else None,
+                                          retraced.data_ptr() if retraced is not None else None,
+                                          _stream_handle(stream)))
+        return hits
 
     def trace_batch(self, jobs, stream=None):
         """jobs: sequence of dicts with keys scene, rays (device [n, 8]), out_id,
