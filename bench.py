@@ -145,7 +145,7 @@ def c5_throughput(ctx, steps, frames=60):
     """Depth-12 ridged terrain (4096^3, ~1.5e8 nodes = 1.2 GB pool, 256
     animated level-4 subtrees): per frame, upload that frame's transforms,
     trace 3840x2160 primary rays, generate 2 cosine-weighted AO rays per
-    pixel on the device and trace them.  Kernel times from HIP events on the
+    pixel on the device, trace them and composite the RGBA8 frame.  Kernel times from HIP events on the
     launch stream; algorithmic bytes per ray from the oracle's counters on a
     sample of the same rays (every 997th)."""
     import torch
@@ -166,7 +166,9 @@ def c5_throughput(ctx, steps, frames=60):
     ao = ctx.ao_rays(rays, prim, k=2, seed=5, radius=64.0)
     out_ao = ctx.trace(h, ao)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    W5, H5 = sc.camera["W"], sc.camera["H"]
+    img = ctx.shade(h, prim.id, W5, H5, ao_id=out_ao.id, k=2)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     w0 = time.perf_counter()
     for k in range(steps):
         e = ev[k]
@@ -178,10 +180,13 @@ def c5_throughput(ctx, steps, frames=60):
         e[2].record(stream)
         ctx.trace_into(h, ao, out_ao.id, out_ao.t, out_ao.inst, out_ao.normal, stream=stream)
         e[3].record(stream)
+        ctx.shade(h, prim.id, W5, H5, ao_id=out_ao.id, k=2, out=img, stream=stream)
+        e[4].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) / steps
     pm = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     am = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
+    sm = float(np.mean([e[3].elapsed_time(e[4]) for e in ev]))
     # algorithmic bytes of the primary trace from the oracle on a sample
     idx = np.arange(0, n, 997)
     hs = oracle.trace_scene(sc, rays_np[idx], frame=0, counters=True)
@@ -196,6 +201,7 @@ def c5_throughput(ctx, steps, frames=60):
            "inline": int(st.n_inline), "kernel": tuned, "steps": steps,
            "primary": {"rays": n, "kernel_ms": round(pm, 4), "mrays_per_s": round(n / pm / 1e3, 2)},
            "ao": {"rays": 2 * n, "kernel_ms": round(am, 4), "mrays_per_s": round(2 * n / am / 1e3, 2)},
+           "shade_ms": round(sm, 4),
            "frame_ms_wall": round(wall * 1e3, 4),
            "roofline_primary": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_ray": round(bpr, 2),

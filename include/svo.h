@@ -238,6 +238,25 @@ typedef struct {
    (a ring of four tables; a fifth call waits for the first to finish). */
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
 
+/* Composite traced hits into an RGBA8 image (the colour field of the
+   paper's hit buffer, Sec. 4.3; images like its Fig. 6).  prim_id: device,
+   width * height * samples ids of primary rays in ray order (8x8 tiles when
+   tiled != 0, else row-major; `samples` consecutive rays per pixel, as
+   svo_generate_primary_rays makes them).  ao_id: device, k ids per primary
+   ray (consecutive, as svo_generate_ao_rays makes them), or NULL when k ==
+   0.  In integers: a sample whose primary id is a node of `scene` has the
+   RGB of that leaf's word1 and, with occ of its k AO rays blocked (id !=
+   SVO_NONE), weight (F k + (1000 - F)(k - occ)) / (1000 k), F =
+   ambient_permille (weight 1 when k == 0); any other id (a miss, a step
+   limit) takes background_rgba with weight 1.  Each channel is the mean of
+   colour * weight over the pixel's samples, rounded half up; alpha 255.
+   out_rgba: device, width * height uint32, row-major (R in the low byte).
+   Errors: SVO_EINVAL (unknown scene, NULL buffer, ambient_permille > 1000),
+   SVO_ERANGE (samples 0 or > 1024, k > 64, too large), SVO_EDEVICE. */
+int svo_shade(svo_ctx* ctx, svo_scene scene, const uint32_t* prim_id, const uint32_t* ao_id, uint32_t width,
+              uint32_t height, uint32_t samples, uint32_t tiled, uint32_t k, uint32_t ambient_permille,
+              uint32_t background_rgba, uint32_t* out_rgba, void* stream);
+
 /* ------------------------------------------------------------------------
  * Launch plans: a batched launch whose kernel arguments are fixed when the
  * plan is created, so that one svo_plan_launch can be captured into a HIP

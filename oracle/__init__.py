@@ -142,3 +142,39 @@ def frames(nodes, root, root_min, root_size, slot_child, slot_cell, fwd):
     if nf < 0:
         raise ValueError("oracle_frames failed with %d" % nf)
     return nf, par, W
+
+
+def shade(nodes, prim_id, ao_id, width, height, samples, k, ambient_permille, background, pixel_index):
+    """Composite hits into an RGBA8 image (the colour field of the paper's hit
+    buffer, Sec. 4.3), written from its definition in integers.
+
+    pixel_index[p]: flat row-major pixel of the p-th pixel in ray order (the
+    input generator's order); samples consecutive rays per pixel, k
+    consecutive AO rays per primary ray.  A sample whose id is a pool node
+    takes that leaf's RGB (word1) with weight (F k + (1000 - F)(k - occ)) /
+    (1000 k), occ = its blocked AO rays (weight 1 if k == 0); otherwise the
+    background with weight 1.  Each channel is the mean over the samples,
+    rounded half up; alpha 255.  Returns uint32 [height, width]."""
+    nodes = np.asarray(nodes, np.uint64)
+    ids = np.asarray(prim_id).astype(np.uint64).reshape(-1)
+    npix = width * height
+    S = int(samples)
+    assert ids.shape[0] == npix * S
+    hit = ids < np.uint64(nodes.shape[0])
+    col = np.full(ids.shape[0], int(background) & 0xFFFFFFFF, np.uint64)
+    col[hit] = nodes[ids[hit].astype(np.int64)] >> np.uint64(32)
+    den = 1000 * max(int(k), 1)
+    w = np.full(ids.shape[0], den, np.int64)
+    if k:
+        occ = (np.asarray(ao_id).astype(np.uint64).reshape(-1, k) != np.uint64(0xFFFFFFFF)).sum(1)
+        wk = int(ambient_permille) * k + (1000 - int(ambient_permille)) * (k - occ.astype(np.int64))
+        w[hit] = wk[hit]
+    out = np.full(npix, 0xFF000000, np.uint64)
+    total = den * S
+    for c in range(3):
+        ch = ((col >> np.uint64(8 * c)) & np.uint64(0xFF)).astype(np.int64)
+        acc = (ch * w).reshape(npix, S).sum(1)
+        out |= (((acc + total // 2) // total).astype(np.uint64) << np.uint64(8 * c))
+    img = np.zeros(npix, np.uint64)
+    img[np.asarray(pixel_index, np.int64)] = out
+    return img.astype(np.uint32).reshape(height, width)

@@ -1490,6 +1490,36 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     return SVO_OK;
 }
 
+int svo_shade(svo_ctx* ctx, svo_scene scene, const uint32_t* prim_id, const uint32_t* ao_id, uint32_t width,
+              uint32_t height, uint32_t samples, uint32_t tiled, uint32_t k, uint32_t ambient_permille,
+              uint32_t background_rgba, uint32_t* out_rgba, void* stream) {
+    if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
+    Scene* S = find_scene(ctx, scene);
+    if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
+    if ((uint64_t)width * height == 0) return SVO_OK;
+    if (!prim_id || !out_rgba || (k && !ao_id)) return fail(SVO_EINVAL, "prim_id, out_rgba (and ao_id when k > 0) are required");
+    if (samples == 0 || samples > 1024 || k > 64) return fail(SVO_ERANGE, "samples must be 1..1024 and k at most 64");
+    if (ambient_permille > 1000) return fail(SVO_EINVAL, "ambient_permille must be at most 1000");
+    if ((uint64_t)width * height * samples * (k ? k : 1) >= (1ull << 40)) return fail(SVO_ERANGE, "image too large");
+    HIP_TRY(hipSetDevice(ctx->device));
+    svo::ShadeArgs a{};
+    a.nodes = S->d_nodes;
+    a.n_nodes = S->n_nodes;
+    a.prim_id = prim_id;
+    a.ao_id = ao_id;
+    a.width = width;
+    a.height = height;
+    a.samples = samples;
+    a.tiled = tiled ? 1u : 0u;
+    a.k = k;
+    a.ambient = ambient_permille;
+    a.background = background_rgba;
+    a.out = out_rgba;
+    const hipError_t e = svo::launch_shade(a, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SVO_EDEVICE, "shade launch failed: %s", hipGetErrorString(e));
+    return SVO_OK;
+}
+
 int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream) {
     if (!ctx || !cam || !out_rays) return fail(SVO_EINVAL, "ctx, cam and out_rays are required");
     if (((uintptr_t)out_rays) & 15u) return fail(SVO_EINVAL, "out_rays must be 16-byte aligned");

@@ -166,6 +166,20 @@ struct AoArgs {
 
 hipError_t launch_ao_rays(const AoArgs& a, hipStream_t stream);
 
+// Compositing into an RGBA8 image (see svo_raygen.hip).
+struct ShadeArgs {
+    const uint64_t* nodes;    // the scene's pool: a leaf's word1 is its RGBA8 colour
+    uint64_t n_nodes;         // ids at or beyond this count as misses
+    const uint32_t* prim_id;  // width * height * samples, ray order
+    const uint32_t* ao_id;    // k per primary ray (nullable when k == 0)
+    uint32_t width, height, samples, tiled, k;
+    uint32_t ambient;         // per mille of the colour kept when every AO ray is blocked
+    uint32_t background;      // RGBA8 of a miss
+    uint32_t* out;            // width * height, row-major
+};
+
+hipError_t launch_shade(const ShadeArgs& a, hipStream_t stream);
+
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block);
 // Allow the trace kernel up to max_lds bytes of dynamic LDS on the current
 // device; done once when a context is created, so that no launch (eager or

@@ -1,6 +1,9 @@
-// Primary-ray generation on the device: one pinhole ray (or `samples`
-// jittered rays) per pixel, in the paper's per-pixel form (Fig. 5: one
-// pixel/ray), written in the 32-byte ray layout the trace kernel reads.
+// Image-space kernels around the trace.  Primary-ray generation on the
+// device: one pinhole ray (or `samples` jittered rays) per pixel, in the
+// paper's per-pixel form (Fig. 5: one pixel/ray), written in the 32-byte ray
+// layout the trace kernel reads; ambient-occlusion rays from primary hits;
+// and compositing hits into an RGBA8 image (the colour field of the paper's
+// hit buffer, Sec. 4.3).
 //
 // Ray order: pixels in 8x8 tiles (tile rows top to bottom, tiles left to
 // right, pixels row-major inside a tile; partial tiles at the right and
@@ -27,26 +30,33 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 
 __device__ __forceinline__ float unit24(uint32_t h) { return (float)(h >> 8) * 0x1p-24f; }
 
+// Pixel (x, y) of the pix-th pixel in ray order: 8x8 tiles (tile rows top
+// to bottom, tiles left to right, row-major inside a tile; partial tiles at
+// the right and bottom edges) or plain row-major.
+__device__ __forceinline__ void pixel_of(uint32_t pix, uint32_t W, uint32_t H, uint32_t tiled, uint32_t& x,
+                                         uint32_t& y) {
+    if (tiled) {
+        const uint32_t ty = pix / (8u * W);
+        uint32_t rem = pix - ty * 8u * W;
+        const uint32_t h = min(8u, H - 8u * ty);
+        const uint32_t tx = rem / (8u * h);
+        rem -= tx * 8u * h;
+        const uint32_t w = min(8u, W - 8u * tx);
+        y = 8u * ty + rem / w;
+        x = 8u * tx + rem % w;
+    } else {
+        y = pix / W;
+        x = pix % W;
+    }
+}
+
 __global__ __launch_bounds__(256) void primary_rays_kernel(CameraArgs c, float4* __restrict__ out) {
     const uint64_t n = (uint64_t)c.width * c.height * c.samples;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t pix = (uint32_t)(i / c.samples);
         const uint32_t smp = (uint32_t)(i % c.samples);
         uint32_t x, y;
-        if (c.tiled) {
-            const uint32_t W = c.width, H = c.height;
-            const uint32_t ty = pix / (8u * W);
-            uint32_t rem = pix - ty * 8u * W;
-            const uint32_t h = min(8u, H - 8u * ty);
-            const uint32_t tx = rem / (8u * h);
-            rem -= tx * 8u * h;
-            const uint32_t w = min(8u, W - 8u * tx);
-            y = 8u * ty + rem / w;
-            x = 8u * tx + rem % w;
-        } else {
-            y = pix / c.width;
-            x = pix % c.width;
-        }
+        pixel_of(pix, c.width, c.height, c.tiled, x, y);
         float fx = 0.5f, fy = 0.5f;
         if (c.jitter) {
             const uint32_t k = mix32(c.seed ^ mix32(pix * 0x9e3779b9u + smp));
@@ -111,7 +121,49 @@ __global__ __launch_bounds__(256) void ao_rays_kernel(AoArgs a) {
     }
 }
 
+// Composite one pixel per thread, in integers: sample i of the pixel has
+// leaf colour c (RGB of the hit leaf's word1; the background for a miss,
+// which is any id outside the pool)
+// and `occ` of its k AO rays blocked; it contributes c * (F k + (1000 - F)
+// (k - occ)) / (1000 k) (weight 1 for a miss), and the pixel is the rounded
+// mean of its samples.  Alpha is 255.
+__global__ __launch_bounds__(256) void shade_kernel(ShadeArgs a) {
+    const uint64_t npix = (uint64_t)a.width * a.height;
+    const uint64_t den = 1000ull * (a.k ? a.k : 1u);
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t acc[3] = {0, 0, 0};
+        for (uint32_t s = 0; s < a.samples; ++s) {
+            const uint64_t i = p * a.samples + s;
+            const uint32_t id = a.prim_id[i];
+            uint32_t col = a.background;
+            uint64_t w = den;
+            if ((uint64_t)id < a.n_nodes) {
+                col = (uint32_t)(a.nodes[id] >> 32);
+                uint32_t occ = 0;
+                for (uint32_t j = 0; j < a.k; ++j) occ += (a.ao_id[i * a.k + j] != 0xFFFFFFFFu) ? 1u : 0u;
+                w = (uint64_t)a.ambient * a.k + (uint64_t)(1000u - a.ambient) * (a.k - occ);
+                if (a.k == 0) w = den;
+            }
+            for (int c = 0; c < 3; ++c) acc[c] += (uint64_t)((col >> (8 * c)) & 0xFFu) * w;
+        }
+        const uint64_t total = den * a.samples;
+        uint32_t x, y;
+        pixel_of((uint32_t)p, a.width, a.height, a.tiled, x, y);
+        uint32_t out = 0xFF000000u;
+        for (int c = 0; c < 3; ++c) out |= (uint32_t)((acc[c] + total / 2) / total) << (8 * c);
+        a.out[(uint64_t)y * a.width + x] = out;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_shade(const ShadeArgs& a, hipStream_t stream) {
+    const uint64_t n = (uint64_t)a.width * a.height;
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65535);
+    hipLaunchKernelGGL(shade_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_ao_rays(const AoArgs& a, hipStream_t stream) {
     const uint64_t n = a.n * a.k;

@@ -28,7 +28,7 @@ MAX_INLINE_NEST = 4
 EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
            "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
-           "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_plan_create", "svo_plan_set_jobs", "svo_plan_launch", "svo_plan_destroy")
+           "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_shade", "svo_plan_create", "svo_plan_set_jobs", "svo_plan_launch", "svo_plan_destroy")
 
 
 class SvoError(RuntimeError):
@@ -121,6 +121,7 @@ def lib():
         "svo_trace_rays": (I, [P, U32, P, U64, P, P, P, P, P]),
         "svo_trace_batch": (I, [P, ctypes.POINTER(Job), U32, P]),
         "svo_trace_rays_reuse": (I, [P, U32, P, U64, P, P, P, P, P, P]),
+        "svo_shade": (I, [P, U32, P, P, U32, U32, U32, U32, U32, U32, U32, P, P]),
         "svo_tune": (I, [P, U32, P, U64, P, ctypes.POINTER(Config)]),
         "svo_generate_primary_rays": (I, [P, ctypes.POINTER(Camera), P, P]),
         "svo_generate_ao_rays": (I, [P, P, P, P, U64, U32, U32, ctypes.c_float, ctypes.c_float, P, P]),
@@ -348,6 +349,17 @@ class Context:
                                           retraced.data_ptr() if retraced is not None else None,
                                           _stream_handle(stream)))
         return hits
+
+    def shade(self, scene: int, prim_id, width: int, height: int, samples: int = 1, tiled: bool = True, ao_id=None,
+              k: int = 0, ambient_permille: int = 200, background=0xFF402010, out=None, stream=None):
+        """RGBA8 image [height, width] (uint32, R in the low byte) from hit ids."""
+        import torch
+        if out is None:
+            out = torch.empty((height, width), dtype=torch.int32, device=prim_id.device)
+        _check(lib().svo_shade(self._ptr, int(scene), prim_id.data_ptr(), ao_id.data_ptr() if ao_id is not None else None,
+                               int(width), int(height), int(samples), int(bool(tiled)), int(k), int(ambient_permille),
+                               int(background) & 0xFFFFFFFF, out.data_ptr(), _stream_handle(stream)))
+        return out
 
     def trace_batch(self, jobs, stream=None):
         """jobs: sequence of dicts with keys scene, rays (device [n, 8]), out_id,

@@ -509,3 +509,34 @@ def test_p7_eq4_sphere_never_drops_a_hit():
         dropped_other += int((meet & _eq4_rejects(b + lo @ A.T, r, o, d, tmin, tmax)).sum())
     assert hits > 10000 and rejected > 10000     # neither side of the test is vacuous
     assert dropped_other > 0
+
+
+def test_shade_hand_worked_example():
+    """Shading pin, worked by hand: leaf colour (200, 100, 50); a pixel with
+    two samples, one a miss on black, one a hit with 1 of k = 2 AO rays
+    blocked and F = 200 per mille: weight (200*2 + 800*1)/2000 = 0.6, so the
+    hit sample is (120, 60, 30) and the pixel mean (60, 30, 15)."""
+    leaf = np.uint64((0xFF << 24 | 50 << 16 | 100 << 8 | 200)) << np.uint64(32)
+    nodes = np.array([np.uint64(0x1), leaf], np.uint64)         # node 1: a leaf (mask 0)
+    NONE = 0xFFFFFFFF
+    # 1x1 image, 2 samples: sample 0 misses, sample 1 hits node 1
+    img = oracle.shade(nodes, [NONE, 1], [0, 0, 0, NONE], 1, 1, 2, 2, 200, 0xFF000000, [0])
+    assert int(img[0, 0]) == (0xFF << 24 | 15 << 16 | 30 << 8 | 60)
+    # no AO: the leaf colour itself; all AO blocked: colour * F / 1000 (rounded half up)
+    assert int(oracle.shade(nodes, [1], None, 1, 1, 1, 0, 200, 0, [0])[0, 0]) == (0xFF << 24 | 50 << 16 | 100 << 8 | 200)
+    img = oracle.shade(nodes, [1], [3, 4, 5], 1, 1, 1, 3, 333, 0, [0])
+    assert int(img[0, 0]) == (0xFF << 24 | 17 << 16 | 33 << 8 | 67)   # 200*.333=66.6, 100*.333=33.3, 50*.333=16.65
+    # a step-limit id is no node: background
+    assert int(oracle.shade(nodes, [0xFFFFFFFE], None, 1, 1, 1, 0, 200, 0xFF0A0B0C, [0])[0, 0]) == 0xFF0A0B0C
+
+
+def test_shade_places_pixels_in_tile_order():
+    from svogen import camera as cam
+    W, H = 13, 10
+    pix = cam.pixel_order(W, H, "tiles")
+    nodes = np.zeros(W * H, np.uint64)
+    nodes[:] = (np.arange(W * H, dtype=np.uint64) | np.uint64(0xFF000000)) << np.uint64(32)   # colour = node index
+    img = oracle.shade(nodes, np.arange(W * H), None, W, H, 1, 0, 0, 0, pix)
+    # ray p hit node p, whose colour encodes p: the pixel at pix[p] holds p
+    flat = img.reshape(-1) & 0xFFFFFF
+    assert np.array_equal(flat[pix], np.arange(W * H))
