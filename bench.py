@@ -193,7 +193,6 @@ def c5_throughput(ctx, steps, frames=60):
     bpr = float((8.0 * hs.nnode.astype(np.float64) + 64.0 * hs.nframe + 32.0 + 24.0).mean())
     achieved = bpr * n / (pm * 1e-3) / 1e9
     st = ctx.scene_stats(h)
-    ctx.free_scene(h)
     res = {"workload": "terrain4096: depth-12 (4096^3) ridged-fBm heightfield SVO, %d nodes (%.2f GB), 256 level-4 "
                        "subtrees animated by 4 jittered keyframes (slerp + log-scale lerp), 3840x2160 primary + 2 "
                        "AO rays per pixel" % (sc.nodes.shape[0], sc.nodes.nbytes / 1e9),
@@ -208,7 +207,45 @@ def c5_throughput(ctx, steps, frames=60):
                                 "sample_rays": int(idx.shape[0])}}
     log("depth-12 terrain: primary %.0f Mrays/s, AO %.0f Mrays/s, %.2f ms/frame" % (
         res["primary"]["mrays_per_s"], res["ao"]["mrays_per_s"], res["frame_ms_wall"]))
-    return res
+    del rays, prim, ao, out_ao, img
+    torch.cuda.empty_cache()
+    return res, sc, h
+
+
+def serve_c5(ctx, c5_scene, c5_handle, n_requests, load):
+    """The depth-12 terrain served beside an instanced-scene stream under a
+    16 GiB device-memory budget: 3840x2160 requests with 2 AO rays per pixel
+    and 1920x1080 requests with 4 AO rays per pixel (AO rays generated from
+    each request's own primary hits, as a second phase), Poisson arrivals at
+    `load` x the measured saturation rate; continuously batched vs one
+    request per launch."""
+    from paper_1911_06001_amd import serve
+    from svogen import scenes
+    inst = scenes.instanced_scene()
+    hi = ctx.upload_scene(inst)
+    ctx.set_transforms(hi, inst.xform(0))
+    entries = {"terrain4096": serve.SceneEntry(c5_handle, c5_scene.xform, c5_scene.camera),
+               "instances4096": serve.SceneEntry(hi, inst.xform, inst.camera)}
+    shapes = {"terrain4096": (3840, 2160, 1, 2), "instances4096": (1920, 1080, 1, 4)}
+    names = list(entries)
+    budget = 16 << 30
+    srv = serve.Server(ctx, entries, hbm_budget=budget)
+    srv.run(serve.poisson_requests(4, 1e9, 60, names, shapes=shapes), "batched")
+    burst = serve.poisson_requests(max(12, n_requests // 4), 1e9, 61, names, shapes=shapes)
+    sat = serve.summarize(srv.run(burst, "batched"))
+    rate = sat["requests"] / sat["makespan_s"]
+    trace = serve.poisson_requests(n_requests, load * rate, 62, names, shapes=shapes)
+    b = serve.summarize(srv.run(trace, "batched"))
+    max_used = srv.scheduler.max_used
+    s1 = serve.summarize(srv.run(trace, "single"))
+    ctx.free_scene(hi)
+    log("serving depth-12 + instances at %.1f load: batched p50 %.1f p99 %.1f ms, single p50 %.1f p99 %.1f ms, "
+        "peak admitted %.1f GiB" % (load, b["p50_ms"], b["p99_ms"], s1["p50_ms"], s1["p99_ms"], max_used / 2**30))
+    return {"requests": n_requests, "offered_load": load, "saturation_rps": round(rate, 2), "hbm_budget_bytes": budget,
+            "peak_admitted_bytes": int(max_used),
+            "mix": "terrain4096 3840x2160 + 2 AO rays/pixel and instances4096 1920x1080 + 4 AO rays/pixel, "
+                   "Poisson arrivals",
+            "batched": b, "single": s1}
 
 
 def serve_latency(ctx, terrain, terrain_handle, n_requests, loads, warm=100):
@@ -442,8 +479,13 @@ def main():
     if not args.no_instances:
         instances = instances_throughput(ctx, max(5, K // 6))
     c5 = None
+    c5_serving = None
     if not args.no_c5:
-        c5 = c5_throughput(ctx, max(5, K // 6))
+        c5, c5_scene, c5_h = c5_throughput(ctx, max(5, K // 6))
+        if args.serve_requests > 0:
+            c5_serving = serve_c5(ctx, c5_scene, c5_h, max(40, args.serve_requests // 10), 0.6)
+        ctx.free_scene(c5_h)
+        del c5_scene
     serving = None
     if args.serve_requests > 0:
         serving = serve_latency(ctx, sc, anim, args.serve_requests, [float(x) for x in args.serve_loads.split(",")])
@@ -477,6 +519,7 @@ def main():
         "serving": serving,
         "instances": instances,
         "terrain4096": c5,
+        "serving_terrain4096_instances": c5_serving,
     }
     ctx.free_scene(anim)
     ctx.free_scene(stat)

@@ -46,14 +46,21 @@ class Request:
     height: int
     samples: int
     seed: int = 0
+    ao: int = 0               # ambient-occlusion rays per primary ray (0: primary rays only)
+    ao_radius: float = 64.0
 
     @property
     def rays(self) -> int:
+        """Primary rays."""
         return self.width * self.height * self.samples
 
     @property
+    def total_rays(self) -> int:
+        return self.rays * (1 + self.ao)
+
+    @property
     def footprint(self) -> int:
-        return self.rays * (RAY_BYTES + OUT_BYTES)
+        return self.total_rays * (RAY_BYTES + OUT_BYTES)
 
 
 @dataclass
@@ -82,9 +89,16 @@ class _Active:
     rays: "object"
     out: dict
     fwd: np.ndarray
-    next_ray: int = 0        # first ray not yet submitted
+    next_ray: int = 0        # first ray of the current phase not yet submitted
     pending_chunks: int = 0  # submitted chunks not yet complete
     frames: int = 1          # frame records one chunk of this request takes
+    n: int = -1              # rays of the current phase (primary, then AO)
+    phase: int = 0           # 0: primary rays; 1: AO rays from the primary hits
+    primary_out: Optional[dict] = None
+
+    def __post_init__(self):
+        if self.n < 0:
+            self.n = self.req.rays
 
 
 class Scheduler:
@@ -122,7 +136,15 @@ class Scheduler:
         self.used = 0
         self.max_used = 0
 
-    def admit(self, waiting: "collections.deque", on_admit: Callable[[Request], object]) -> list:
+    def admit(self, waiting: "collections.deque", on_admit: Callable[[Request], object],
+              frames_of: Optional[Callable[[Request], int]] = None) -> list:
+        """frames_of(req): frame records one chunk of req takes; a request that
+        could never fit a step is rejected instead of waiting forever."""
+        if frames_of is not None:
+            for req in waiting:
+                if frames_of(req) > self.max_frames:
+                    raise ValueError("request %d needs %d frame records per step, the limit is %d" %
+                                     (req.rid, frames_of(req), self.max_frames))
         admitted = []
         while waiting and self.used + waiting[0].footprint <= self.budget:
             req = waiting.popleft()
@@ -139,9 +161,9 @@ class Scheduler:
 
     def plan(self, active: list) -> list:
         """[(active, lo, hi)] within the step limits; advances next_ray."""
-        work = [a for a in active if a.req.rays > a.next_ray]
+        work = [a for a in active if a.n > a.next_ray]
         if self.policy == "edf":
-            work.sort(key=lambda a: a.req.arrival + self.slack * a.req.rays / self.ref_rate)
+            work.sort(key=lambda a: a.req.arrival + self.slack * a.req.total_rays / self.ref_rate)
         chunks, left, frames = [], self.max_rays, 0
         share = left
         if self.policy == "fair" and work:
@@ -149,7 +171,7 @@ class Scheduler:
         for a in work:
             if left <= 0 or len(chunks) >= self.max_jobs or frames + a.frames > self.max_frames:
                 break
-            k = min(a.req.rays - a.next_ray, share, left)
+            k = min(a.n - a.next_ray, share, left)
             chunks.append((a, a.next_ray, a.next_ray + k))
             a.next_ray += k
             a.pending_chunks += 1
@@ -160,17 +182,24 @@ class Scheduler:
 
 def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: int = 60,
                      resolutions=((256, 256), (1280, 720), (1920, 1080), (2048, 1152)),
-                     samples=(1, 5)) -> List[Request]:
+                     samples=(1, 5), shapes: Optional[Dict[str, tuple]] = None) -> List[Request]:
     """Seeded Poisson arrival trace with uniformly drawn scene, frame,
-    resolution and rays per pixel."""
+    resolution and rays per pixel; `shapes` fixes (width, height, samples,
+    AO rays per primary ray) per scene instead."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, n)
     t = np.cumsum(gaps) - gaps[0]
     out = []
     for i in range(n):
         W, H = resolutions[rng.integers(0, len(resolutions))]
-        out.append(Request(i, float(t[i]), scenes[rng.integers(0, len(scenes))], int(rng.integers(0, frames)),
-                           int(W), int(H), int(rng.integers(samples[0], samples[1] + 1)), int(rng.integers(0, 2**31))))
+        sc = scenes[rng.integers(0, len(scenes))]
+        f = int(rng.integers(0, frames))
+        spp = int(rng.integers(samples[0], samples[1] + 1))
+        sd = int(rng.integers(0, 2**31))
+        ao = 0
+        if shapes is not None:
+            W, H, spp, ao = shapes[sc]
+        out.append(Request(i, float(t[i]), sc, f, int(W), int(H), int(spp), sd, int(ao)))
     return out
 
 
@@ -191,7 +220,8 @@ class Server:
         self.dev = torch.device("cuda:%d" % ctx.device)
         self.frames = {k: 1 + ctx.scene_stats(e.handle).n_slots for k, e in scenes.items()}
         self.max_jobs = int(max_jobs)
-        self.max_frames = int(max_frames)
+        # room for at least two jobs of the largest scene per step
+        self.max_frames = max(int(max_frames), 2 * max(self.frames.values()))
         self.graph = bool(graph)
         self._plans = []
         self._graphs = []
@@ -235,6 +265,16 @@ class Server:
                     out_t=t.empty(n, dtype=t.float32, device=self.dev),
                     out_normal=t.empty((n, 3), dtype=t.float32, device=self.dev))
 
+    def _start_ao(self, a: "_Active"):
+        """Second phase of a request: AO rays from its primary hits, generated
+        on the device (stream-ordered after the primary trace)."""
+        from .svo import Hits
+        hits = Hits(a.out["out_id"], a.out["out_inst"], a.out["out_t"], a.out["out_normal"])
+        ao = self.ctx.ao_rays(a.rays, hits, k=a.req.ao, seed=a.req.seed, radius=a.req.ao_radius, stream=self.stream)
+        a.primary_out, a.primary_rays = a.out, a.rays
+        a.rays, a.out = ao, self._buffers(ao.shape[0])
+        a.phase, a.n, a.next_ray = 1, ao.shape[0], 0
+
     def run(self, requests: List[Request], mode: str = "batched") -> List[Result]:
         if mode == "batched":
             return self._run_batched(requests)
@@ -277,15 +317,20 @@ class Server:
                 done_at = start_ev.elapsed_time(ev) * 1e-3
                 for a, _, _ in chunks:
                     a.pending_chunks -= 1
-                    if a.pending_chunks == 0 and a.next_ray >= a.req.rays:
+                    if a.pending_chunks == 0 and a.next_ray >= a.n:
+                        if a.phase == 0 and a.req.ao:
+                            self._start_ao(a)
+                            continue
                         a.res.completed = done_at
                         if self.keep:
-                            a.res.out = a.out
-                            a.res.out["rays"] = a.rays
+                            a.res.out = a.primary_out or a.out
+                            a.res.out["rays"] = a.primary_rays if a.phase else a.rays
+                            if a.phase:
+                                a.res.out["ao"] = dict(a.out, rays=a.rays)
                         results.append(a.res)
                         active.remove(a)
                         sched.release(a.req)
-            sched.admit(waiting, on_admit)
+            sched.admit(waiting, on_admit, lambda r: self.frames[r.scene])
             # submit one step when a slot is free and there is work
             if len(inflight) < self.inflight_steps:
                 chunks = sched.plan(active)
@@ -339,6 +384,14 @@ class Server:
             self.ctx.set_transforms(entry.handle, entry.xform(req.frame), stream=self.stream)
             self.ctx.trace_into(entry.handle, rays, out["out_id"], out["out_t"], out["out_inst"], out["out_normal"],
                                 stream=self.stream)
+            if req.ao:
+                from .svo import Hits
+                hits = Hits(out["out_id"], out["out_inst"], out["out_t"], out["out_normal"])
+                ao = self.ctx.ao_rays(rays, hits, k=req.ao, seed=req.seed, radius=req.ao_radius, stream=self.stream)
+                ao_out = self._buffers(ao.shape[0])
+                self.ctx.trace_into(entry.handle, ao, ao_out["out_id"], ao_out["out_t"], ao_out["out_inst"],
+                                    ao_out["out_normal"], stream=self.stream)
+                out["ao"] = dict(ao_out, rays=ao)
             ev = t.cuda.Event(enable_timing=True)
             ev.record(self.stream)
             ev.synchronize()
@@ -352,7 +405,7 @@ class Server:
 
 def summarize(results: List[Result]) -> dict:
     lat = np.array([r.latency for r in results]) * 1e3
-    rays = sum(r.req.rays for r in results)
+    rays = sum(r.req.total_rays for r in results)
     span = max(r.completed for r in results) - min(r.req.arrival for r in results)
     return dict(requests=len(results), p50_ms=round(float(np.percentile(lat, 50)), 3),
                 p99_ms=round(float(np.percentile(lat, 99)), 3), mean_ms=round(float(lat.mean()), 3),

@@ -77,3 +77,31 @@ def test_single_mode_baseline_runs(setup):
     st = serve.summarize(res)
     _say("single", st)
     assert st["requests"] == 8 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_requests_with_ao_phase(setup, graph):
+    """Requests whose AO rays (from their own primary hits) form a second
+    phase: both phases equal tracing them alone."""
+    torch, ctx, entries, scenes = setup
+    from paper_1911_06001_amd import serve
+    shapes = {"sphere": (48, 40, 2, 3), "terrain": (120, 72, 1, 2)}
+    reqs = serve.poisson_requests(12, 3000.0, 8, ["sphere", "terrain"], shapes=shapes)
+    budget = 3 * max(r.footprint for r in reqs)
+    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=20000, keep_outputs=True, graph=graph)
+    try:
+        res = srv.run(reqs, mode="batched")
+    finally:
+        srv.close()
+    _say("ao phase graph=%s" % graph, serve.summarize(res))
+    assert len(res) == len(reqs) and srv.scheduler.max_used <= budget
+    for r in res:
+        e = entries[r.req.scene]
+        ctx.set_transforms(e.handle, e.xform(r.req.frame))
+        prim = ctx.trace(e.handle, r.out["rays"])
+        ao_rays = ctx.ao_rays(r.out["rays"], prim, k=r.req.ao, seed=r.req.seed, radius=r.req.ao_radius)
+        ao = ctx.trace(e.handle, ao_rays)
+        torch.cuda.synchronize()
+        assert torch.equal(r.out["out_id"], prim.id) and torch.equal(r.out["out_t"], prim.t)
+        assert torch.equal(r.out["ao"]["rays"], ao_rays)
+        assert torch.equal(r.out["ao"]["out_id"], ao.id) and torch.equal(r.out["ao"]["out_t"], ao.t)

@@ -104,3 +104,14 @@ def test_edf_orders_by_deadline():
     s.admit(collections.deque([late]), adm)
     nxt = s.plan(active)
     assert nxt[0][0].req.rid == 0                         # the big request is not passed again
+
+
+def test_request_that_cannot_fit_a_step_is_rejected():
+    """A request whose chunk needs more frame records than a step allows
+    would never be planned: admission refuses it instead of waiting."""
+    s = Scheduler(10**12, max_rays=1 << 20, max_frames=64)
+    big = Request(0, 0.0, "deep", 0, 64, 64, 1)
+    with pytest.raises(ValueError):
+        s.admit(collections.deque([big]), lambda r: r, frames_of=lambda r: 257)
+    ok = Request(1, 0.0, "small", 0, 64, 64, 1)
+    assert len(s.admit(collections.deque([ok]), lambda r: r, frames_of=lambda r: 9)) == 1
