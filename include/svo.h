@@ -55,7 +55,8 @@
  *   (the inverse transpose of W_F applied to the local face normal,
  *   normalised), zero when the ray starts inside the leaf.  A miss returns
  *   id = inst = SVO_NONE, t = +inf, normal = 0.  Rays with a non-finite
- *   component, a zero direction or tmin > tmax miss.  The direction is never
+ *   component, a direction below 2^-100 in every component or tmin > tmax
+ *   miss.  The direction is never
  *   renormalised: t is in units of the caller's d.
  *
  * The device computes in FP32.  Rays within a few ulps of an edge, a face
@@ -121,10 +122,8 @@ typedef struct {
     uint32_t lds_cache_nodes;   /* first N pool nodes (the top levels, breadth-first) kept in LDS */
     uint32_t refill_lanes;      /* 0 or 64: a wave takes 64-ray tiles; 1..63: claim new rays once that many lanes are idle */
     uint32_t step_limit;        /* node steps per ray before SVO_STEP_LIMIT */
-    uint32_t sync_lanes;        /* 0 or 64: a wave's lanes leave the walk loop together once all wait; 1..63: once that
-                                   many lanes wait (a hit, a frame change, or no ray), the others pausing mid-walk */
     uint32_t claim_tiles;       /* 64-ray tiles a wave takes from the work queue at once (0: 2; at most 64) */
-    uint32_t reserved[1];
+    uint32_t reserved[2];
 } svo_config;
 
 /* ABI version the library was built with (SVO_ABI_VERSION). */

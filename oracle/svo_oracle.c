@@ -33,7 +33,8 @@
  * notes): no clipping of moved content to its static cell (union of rigid
  * bodies); d_F is never renormalised; an axis with d_a = 0 gives the slab
  * (-inf, inf) when lo <= o_a <= hi and the empty set otherwise; a ray with a
- * non-finite component, a zero direction or tmin > tmax misses.
+ * non-finite component, a zero direction (below 2^-100 in every component)
+ * or tmin > tmax misses.
  *
  * Pool format: 64-bit nodes, bits 0..7 child mask (octant i = x|y<<1|z<<2),
  * bits 8..31 relative child offset c24, bits 32..63 word1.  mask == 0: solid
@@ -431,7 +432,8 @@ static void trace_one(const oscene* sc, const float* ray, int want_margin, doubl
     for (int a = 0; a < 3; ++a)
         if (!isfinite(o[a]) || !isfinite(d[a])) return;
     if (isnan(tmin) || isnan(tmax) || tmin > tmax || tmin == INFINITY) return;
-    if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) return;
+    /* a direction below 2^-100 in every component counts as zero */
+    if (fabs(d[0]) < 0x1p-100 && fabs(d[1]) < 0x1p-100 && fabs(d[2]) < 0x1p-100) return;
 
     ohit best;
     memset(&best, 0, sizeof best);

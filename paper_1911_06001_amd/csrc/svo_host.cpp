@@ -371,7 +371,6 @@ svo_config default_config() {
     c.lds_cache_nodes = 1024;
     c.refill_lanes = 48;
     c.step_limit = 1u << 20;
-    c.sync_lanes = 64;
     c.claim_tiles = 2;
     return c;
 }
@@ -381,7 +380,6 @@ int check_config(const svo_config& c) {
     if (c.blocks_per_cu < 1 || c.blocks_per_cu > 32) return fail(SVO_EINVAL, "blocks_per_cu must be 1..32");
     if (c.lds_cache_nodes > 16384) return fail(SVO_EINVAL, "lds_cache_nodes must be <= 16384");
     if (c.step_limit < 1) return fail(SVO_EINVAL, "step_limit must be >= 1");
-    if (c.sync_lanes > 64) return fail(SVO_EINVAL, "sync_lanes must be <= 64");
     if (c.claim_tiles > 64) return fail(SVO_EINVAL, "claim_tiles must be <= 64");
     return SVO_OK;
 }
@@ -962,7 +960,6 @@ int launch(svo_ctx* ctx, const svo_config& c, svo::TraceArgs& a, hipStream_t st)
 void fill_common(const svo_config& c, svo::TraceArgs& a) {
     a.refill = (c.refill_lanes == 0 || c.refill_lanes > 64) ? 64u : c.refill_lanes;
     a.claim = 64u * ((c.claim_tiles == 0) ? 2u : c.claim_tiles);
-    a.sync = (c.sync_lanes == 0 || c.sync_lanes > 64) ? 64u : c.sync_lanes;
     a.step_limit = c.step_limit;
 }
 

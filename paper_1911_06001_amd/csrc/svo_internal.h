@@ -130,7 +130,6 @@ struct TraceArgs {
     uint32_t reuse;           // 1: the outputs hold the previous trace of these rays (hit buffer)
     unsigned long long* retraced;  // reuse: rays traced again are added here (nullable)
     uint64_t tile_stride;     // claim i covers tile (i * tile_stride) mod tiles (coprime: a permutation)
-    uint32_t sync;            // waiting lanes (events or idle) at which a wave leaves the walk loop (1..64)
     uint32_t step_limit;
 };
 

@@ -60,6 +60,18 @@ struct FrameRay {
 };
 
 __device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
+
+// Reciprocal, square root and reciprocal square root on the hardware units
+// (v_rcp_f32, v_sqrt_f32, v_rsq_f32: about 1 ulp) instead of the correctly
+// rounded sequences.  Uses: the walk's plane parameters (one reciprocal per
+// axis, used for every plane, so the walk stays self-consistent and
+// monotone), the inflated bounding-sphere test and normals.  Arguments stay
+// in the normal range: rays whose direction is below 2^-100 in every
+// component miss (ray_valid), and a frame's clamped components are at least
+// 2^-21 of its largest.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
 // Map the ray into frame F and clip it to the root cell [0, 2^K)^3 and
@@ -82,9 +94,9 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
     if (fabsf(dy) < eps) dy = copysignf(eps, dy);
     if (fabsf(dz) < eps) dz = copysignf(eps, dz);
     fr.flip = (dx < 0.f ? 1u : 0u) | (dy < 0.f ? 2u : 0u) | (dz < 0.f ? 4u : 0u);
-    fr.ix = 1.0f / fabsf(dx);
-    fr.iy = 1.0f / fabsf(dy);
-    fr.iz = 1.0f / fabsf(dz);
+    fr.ix = rcp_fast(fabsf(dx));
+    fr.iy = rcp_fast(fabsf(dy));
+    fr.iz = rcp_fast(fabsf(dz));
     fr.bx = -((dx < 0.f) ? (N - gx) : gx) * fr.ix;
     fr.by = -((dy < 0.f) ? (N - gy) : gy) * fr.iy;
     fr.bz = -((dz < 0.f) ? (N - gz) : gz) * fr.iz;
@@ -113,10 +125,11 @@ __device__ __forceinline__ bool sphere_may_hit(const float4 sp, const Ray& r, fl
     const float tca = fmaf(lx, r.dx, fmaf(ly, r.dy, lz * r.dz));
     const float rr = sp.w * 1.0001f;
     const float r2 = fmaf(rr, rr, 1e-6f * ll);
-    const float perp2 = ll - tca * tca / dd;            // squared distance of the line from the centre
+    const float idd = rcp_fast(dd);
+    const float perp2 = ll - tca * tca * idd;           // squared distance of the line from the centre
     if (perp2 > r2) return false;
-    const float half = sqrtf(fmaxf(r2 - perp2, 0.f) / dd);  // half chord, in t
-    const float tc = tca / dd;                            // t of the closest approach
+    const float half = sqrt_fast(fmaxf(r2 - perp2, 0.f) * idd);  // half chord, in t
+    const float tc = tca * idd;                                    // t of the closest approach
     return (tc - half <= tlimit) && (tc + half >= r.tmin);
 }
 
@@ -135,7 +148,7 @@ __device__ __forceinline__ float box_entry(const BvhNode& B, const Ray& r, float
 __device__ __forceinline__ bool ray_valid(const Ray& r) {
     const bool fin = isfinite(r.ox) && isfinite(r.oy) && isfinite(r.oz) && isfinite(r.dx) && isfinite(r.dy) &&
                      isfinite(r.dz);
-    const bool nonzero = (r.dx != 0.f) || (r.dy != 0.f) || (r.dz != 0.f);
+    const bool nonzero = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) >= 0x1p-100f;
     return fin && nonzero && !isnan(r.tmin) && !isnan(r.tmax) && r.tmin <= r.tmax && r.tmin < INFINITY;
 }
 
@@ -254,7 +267,6 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
 
     const uint32_t refill = a.refill;
     const uint32_t claim = a.claim;
-    const uint32_t sync = a.sync;
     // partition-local ray indices run to part_len (whole tiles); a wave owns
     // the claimed range [rlo, rhi) of partition q (wave-uniform state)
     const uint64_t n_tiles = (n_rays + 63) >> 6;
@@ -356,9 +368,9 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
         }
         // any candidate box in front of the previous hit?
         const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
-        const float ix = 1.0f / (fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
-        const float iy = 1.0f / (fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
-        const float iz = 1.0f / (fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
+        const float ix = rcp_fast(fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
+        const float iy = rcp_fast(fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
+        const float iz = rcp_fast(fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
         uint32_t sp = 0;
         if (box_entry(lds_bvh[bbase], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(0u, 0u);
         while (sp > 0u) {
@@ -385,7 +397,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
             const float* row = &lds_frames[best_f].m[4 * best_axis];
             const float da = fmaf(row[0], r.dx, fmaf(row[1], r.dy, row[2] * r.dz));
             const float s = (da < 0.f) ? 1.f : -1.f;
-            const float inv = s / sqrtf(fmaf(row[0], row[0], fmaf(row[1], row[1], row[2] * row[2])));
+            const float inv = s * rsq_fast(fmaf(row[0], row[0], fmaf(row[1], row[1], row[2] * row[2])));
             nx = row[0] * inv;
             ny = row[1] * inv;
             nz = row[2] * inv;
@@ -506,9 +518,9 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                         } else if (ncand) {
                             // tiny components clamped as in frame_setup, so no 0 * inf
                             const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
-                            wix = 1.0f / (fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
-                            wiy = 1.0f / (fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
-                            wiz = 1.0f / (fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
+                            wix = rcp_fast(fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
+                            wiy = rcp_fast(fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
+                            wiz = rcp_fast(fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
                             const float e = box_entry(lds_bvh[bbase], r, wix, wiy, wiz, tl);
                             if (e < INFINITY) {
                                 bst[0] = make_uint2(0u, __float_as_uint(e));
@@ -565,71 +577,63 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
                 ev = advance(ex, ey, ez, min3f(ex, ey, ez));
             }
-            // the hot loop: visit, descend or advance until something happens.
-            // A lane with an event stops walking; the wave leaves the loop
-            // together once `sync` lanes wait (events, or not walking), and
-            // lanes still mid-walk pause there and resume on the next pass.
-            for (;;) {
-                if (ev == EV_NONE) {
-                    if (++steps > a.step_limit) {
-                        ev = EV_LIMIT;
-                    } else {
-                        const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
-                        const float ey = fmaf((float)(py + size), fr.iy, fr.by);
-                        const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
-                        const float tc1 = min3f(ex, ey, ez);
-                        const uint32_t oct =
-                            (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
-                        bool adv = true;
-                        if ((pmask >> oct) & 1u) {
-                            const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
-                            // the child's corner does not depend on the node:
-                            // computed while its load is in flight
-                            const uint32_t hs = size >> 1;
-                            const uint32_t cx = px + ((fmaf((float)(px + hs), fr.ix, fr.bx) <= tc0) ? hs : 0u);
-                            const uint32_t cy = py + ((fmaf((float)(py + hs), fr.iy, fr.by) <= tc0) ? hs : 0u);
-                            const uint32_t cz = pz + ((fmaf((float)(pz + hs), fr.iz, fr.bz) <= tc0) ? hs : 0u);
-                            // separate LDS and global reads (a select between the two
-                            // would become one generic load waiting on both counters)
-                            uint64_t wl = 0, wg = 0;
-                            if (n_lds) wl = lds_nodes[min(cidx, n_lds - 1u)];
-                            if (cidx >= n_lds) wg = gld(nodes, cidx);
-                            const uint64_t w = (cidx < n_lds) ? wl : wg;
-                            const uint32_t w0 = (uint32_t)w;
-                            const uint32_t w1 = (uint32_t)(w >> 32);
-                            const uint32_t cm = w0 & 0xFFu;
-                            if (cm == 0u) {
-                                ev = EV_HIT;
-                                hit_id = cidx;
-                                adv = false;
-                            } else if (!(w1 & kXform)) {
-                                stkc[(sbase + lvl) * 64] = pchild;
-                                stkm[(sbase + lvl) * 64] = (uint8_t)pmask;
-                                const uint32_t c24 = w0 >> 8;
-                                pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
-                                pmask = cm;
-                                ++lvl;
-                                size = hs;
-                                px = cx;
-                                py = cy;
-                                pz = cz;
-                                adv = false;
-                            } else {
-                                const uint32_t f = fbase + 1u + (w1 & 0x7FFFFFFFu);
-                                if (lds_frames[f].info & FR_INLINE) {
-                                    ev = EV_ENTER;
-                                    xf = f;
-                                    xf_tc1 = tc1;
-                                    adv = false;
-                                }
-                                // else a candidate frame: traced on its own, empty here
-                            }
-                        }
-                        if (adv) ev = advance(ex, ey, ez, tc1);
-                    }
+            // the hot loop: visit, descend or advance until something happens
+            while (ev == EV_NONE) {
+                if (++steps > a.step_limit) {
+                    ev = EV_LIMIT;
+                    break;
                 }
-                const uint64_t busy = __ballot(ev == EV_NONE);
-                if (busy == 0ull || 64u - (uint32_t)__popcll(busy) >= sync) break;
+                const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
+                const float ey = fmaf((float)(py + size), fr.iy, fr.by);
+                const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
+                const float tc1 = min3f(ex, ey, ez);
+                const uint32_t oct =
+                    (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
+                if ((pmask >> oct) & 1u) {
+                    const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
+                    // the child's corner does not depend on the node: computed
+                    // while its load is in flight
+                    const uint32_t hs = size >> 1;
+                    const uint32_t cx = px + ((fmaf((float)(px + hs), fr.ix, fr.bx) <= tc0) ? hs : 0u);
+                    const uint32_t cy = py + ((fmaf((float)(py + hs), fr.iy, fr.by) <= tc0) ? hs : 0u);
+                    const uint32_t cz = pz + ((fmaf((float)(pz + hs), fr.iz, fr.bz) <= tc0) ? hs : 0u);
+                    // separate LDS and global reads (a select between the two
+                    // would become one generic load waiting on both counters)
+                    uint64_t wl = 0, wg = 0;
+                    if (n_lds) wl = lds_nodes[min(cidx, n_lds - 1u)];
+                    if (cidx >= n_lds) wg = gld(nodes, cidx);
+                    const uint64_t w = (cidx < n_lds) ? wl : wg;
+                    const uint32_t w0 = (uint32_t)w;
+                    const uint32_t w1 = (uint32_t)(w >> 32);
+                    const uint32_t cm = w0 & 0xFFu;
+                    if (cm == 0u) {
+                        ev = EV_HIT;
+                        hit_id = cidx;
+                        break;
+                    }
+                    if (!(w1 & kXform)) {
+                        stkc[(sbase + lvl) * 64] = pchild;
+                        stkm[(sbase + lvl) * 64] = (uint8_t)pmask;
+                        const uint32_t c24 = w0 >> 8;
+                        pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
+                        pmask = cm;
+                        ++lvl;
+                        size = hs;
+                        px = cx;
+                        py = cy;
+                        pz = cz;
+                        continue;
+                    }
+                    const uint32_t f = fbase + 1u + (w1 & 0x7FFFFFFFu);
+                    if (lds_frames[f].info & FR_INLINE) {
+                        ev = EV_ENTER;
+                        xf = f;
+                        xf_tc1 = tc1;
+                        break;
+                    }
+                    // a candidate frame: traced on its own, empty here
+                }
+                ev = advance(ex, ey, ez, tc1);
             }
             if (ev == EV_HIT) {
                 // the first solid leaf front to back ends this top-level frame
