@@ -318,9 +318,10 @@ int svo_plan_destroy(svo_ctx* ctx, svo_plan* plan);
 int svo_get_config(svo_ctx* ctx, svo_config* cfg);
 int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
 
-/* Autotuner.  Times candidate kernel configurations (waves per work-group,
-   resident work-groups per CU, LDS pool-prefix size, lane refill, tiles per
-   work-queue claim) on n device sample rays against `scene` under its current transforms, keeps
+/* Autotuner.  Times candidate kernel configurations on n device sample rays
+   against `scene` under its current transforms, in two stages: the launch
+   shape (waves per work-group, work-groups per CU, LDS pool-prefix size),
+   then lane refill and tiles per work-queue claim for the fastest shape.  Keeps
    the fastest for that scene -- later svo_trace_rays calls on it use it, and
    a batch uses it when that scene holds most of the batch's rays -- and
    writes it to *best (nullable).  Results never depend on the

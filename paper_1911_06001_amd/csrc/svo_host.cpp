@@ -1424,51 +1424,68 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     const svo_config was_cfg = S->cfg;
     svo_config win = base;
     float win_ms = 1e30f;
+    // Two stages: the launch shape (waves per work-group, work-groups per
+    // CU, LDS node cache) at whole-tile refill and 2-tile claims, then
+    // refill and claim size for the winning shape.
     static const uint32_t kWaves[] = {4, 8, 16};
-    static const uint32_t kBlocks[] = {1, 2, 3, 4, 6, 8};
-    static const uint32_t kCache[] = {1024, 4096};
+    static const uint32_t kBlocks[] = {1, 2, 3, 4, 5, 6, 8};
+    static const uint32_t kCache[] = {1024, 2048, 4096};
     static const uint32_t kRefill[] = {0, 48};
     static const uint32_t kClaim[] = {1, 2, 4};
+    auto time_cand = [&](const svo_config& cand, float& ms) -> int {
+        S->tuned = true;
+        S->cfg = cand;
+        int r = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
+        if (r) return r;  // SVO_ERANGE: does not fit in LDS
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(SVO_EDEVICE, "tuner event record failed");
+        for (int k = 0; k < 3 && r == SVO_OK; ++k)
+            r = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
+        if (r) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(SVO_EDEVICE, "tuner timing failed");
+        return SVO_OK;
+    };
+    int rc = SVO_OK;
+    auto try_all = [&](const std::vector<svo_config>& cands) {
+        for (const svo_config& cand : cands) {
+            float ms = 0.f;
+            rc = time_cand(cand, ms);
+            if (rc == SVO_ERANGE) continue;
+            if (rc) return;
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = cand;
+            }
+        }
+    };
     std::vector<svo_config> cands;
     for (uint32_t w : kWaves)
         for (uint32_t b : kBlocks) {
             if (w * b > 32) continue;  // resident waves per CU
-            for (uint32_t c : kCache)
-                for (uint32_t r : kRefill)
-                    for (uint32_t y : kClaim) {
-                        svo_config cand = base;
-                        cand.waves_per_block = w;
-                        cand.blocks_per_cu = b;
-                        cand.lds_cache_nodes = c;
-                        cand.refill_lanes = r;
-                        cand.claim_tiles = y;
-                        cands.push_back(cand);
-                    }
+            for (uint32_t c : kCache) {
+                svo_config cand = base;
+                cand.waves_per_block = w;
+                cand.blocks_per_cu = b;
+                cand.lds_cache_nodes = c;
+                cand.refill_lanes = 0;
+                cand.claim_tiles = 2;
+                cands.push_back(cand);
+            }
         }
-    int rc = SVO_OK;
-    for (const svo_config& cand : cands) {
-        S->tuned = true;
-        S->cfg = cand;
-        rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
-        if (rc == SVO_ERANGE) continue;  // does not fit in LDS
-        if (rc) break;
-        if (hipEventRecord(e0, st) != hipSuccess) {
-            rc = fail(SVO_EDEVICE, "tuner event record failed");
-            break;
-        }
-        for (int k = 0; k < 3 && rc == SVO_OK; ++k)
-            rc = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
-        if (rc) break;
-        float ms = 0.f;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = fail(SVO_EDEVICE, "tuner timing failed");
-            break;
-        }
-        if (ms < win_ms) {
-            win_ms = ms;
-            win = cand;
-        }
+    try_all(cands);
+    if (rc == SVO_OK || rc == SVO_ERANGE) {
+        const svo_config shape = win;
+        cands.clear();
+        for (uint32_t r : kRefill)
+            for (uint32_t y : kClaim) {
+                if (r == shape.refill_lanes && y == shape.claim_tiles) continue;
+                svo_config cand = shape;
+                cand.refill_lanes = r;
+                cand.claim_tiles = y;
+                cands.push_back(cand);
+            }
+        try_all(cands);
     }
     cleanup();
     if (rc && rc != SVO_ERANGE) {

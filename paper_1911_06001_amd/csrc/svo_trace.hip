@@ -184,6 +184,11 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
     return shared + per_wave * waves_per_block;
 }
 
+// kSorted: every job's candidates go through the per-lane entry table (at
+// most 16 of them); otherwise through the per-frame box hierarchy.  A launch
+// uses one of the two, and each instantiation carries only its own path,
+// which keeps the sorted one at fewer registers (more resident waves).
+template <bool kSorted>
 __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* p = smem;
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
         for (uint32_t i = 0; i < nin; ++i)
             if (may_reach(lds_cand[cbase + ncand + i], tlim)) return false;
         if (ncand == 0) return true;
-        if (a.sort_cand) {
+        if (kSorted) {
             for (uint32_t c = 0; c < ncand; ++c)
                 if (may_reach(lds_cand[cbase + c], tlim)) return false;
             return true;
@@ -503,7 +508,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     } else {
                         retrace = true;
                         tl = r.tmax;
-                        if (a.sort_cand) {
+                        if (kSorted) {
                             for (uint32_t c = 0; c < ncand; ++c) {
                                 const uint32_t f = lds_cand[cbase + c];
                                 float e = INFINITY;
@@ -542,12 +547,13 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
             // Leave the current cell through its nearest exit plane(s); EV_END
             // when the ray leaves the frame's root cell or passes tl.
             auto advance = [&](float ex, float ey, float ez, float tc1) -> uint32_t {
-                const uint32_t step = (ex == tc1 ? 1u : 0u) | (ey == tc1 ? 2u : 0u) | (ez == tc1 ? 4u : 0u);
-                if (tc1 > tl || step == 0u) return EV_END;
-                const uint32_t nx = px + ((step & 1u) ? size : 0u);
-                const uint32_t ny = py + ((step & 2u) ? size : 0u);
-                const uint32_t nz = pz + ((step & 4u) ? size : 0u);
+                const bool sx = ex == tc1, sy = ey == tc1, sz = ez == tc1;
+                if (tc1 > tl) return EV_END;
+                const uint32_t nx = px + (sx ? size : 0u);
+                const uint32_t ny = py + (sy ? size : 0u);
+                const uint32_t nz = pz + (sz ? size : 0u);
                 const uint32_t diff = (nx ^ px) | (ny ^ py) | (nz ^ pz);
+                // no plane at tc1 (a NaN) leaves diff = 0, h = 2^32 - 1: the walk ends
                 const uint32_t h = 31u - __clz(diff);
                 if (h >= fr.K) return EV_END;  // left the frame's root cell
                 const uint32_t nsize = 1u << h;
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                 lvl = nlvl;
                 size = nsize;
                 tc0 = tc1;
-                eaxis = __ffs(step) - 1;
+                eaxis = sx ? 0 : (sy ? 1 : 2);   // the lowest axis crossed
                 return EV_NONE;
             };
             uint32_t ev = EV_NONE;
@@ -587,9 +593,11 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                 const float ey = fmaf((float)(py + size), fr.iy, fr.by);
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
                 const float tc1 = min3f(ex, ey, ez);
-                const uint32_t oct =
-                    (((px & size) ? 1u : 0u) | ((py & size) ? 2u : 0u) | ((pz & size) ? 4u : 0u)) ^ fr.flip;
-                if ((pmask >> oct) & 1u) {
+                // the cell's octant in its parent: bit h of each corner (size = 2^h)
+                const uint32_t h = fr.K - lvl;
+                const uint32_t oct = (__builtin_amdgcn_ubfe(px, h, 1) | (__builtin_amdgcn_ubfe(py, h, 1) << 1) |
+                                      (__builtin_amdgcn_ubfe(pz, h, 1) << 2)) ^ fr.flip;
+                if (__builtin_amdgcn_ubfe(pmask, oct, 1)) {
                     const uint32_t cidx = pchild + __popc(pmask & ((1u << oct) - 1u));
                     // the child's corner does not depend on the node: computed
                     // while its load is in flight
@@ -700,7 +708,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                 continue;
             }
             // ------------------------------------------------------ next candidate frame
-            if (a.sort_cand) {
+            if (kSorted) {
                 float bc = INFINITY;
                 int pick = -1;
                 for (uint32_t c = 0; c < ncand; ++c) {
@@ -780,12 +788,18 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
 }
 
 hipError_t prepare_trace(size_t max_lds) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds);
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel<true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
 }
 
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream) {
-    hipLaunchKernelGGL(trace_kernel, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
+    if (a.sort_cand)
+        hipLaunchKernelGGL(trace_kernel<true>, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
+    else
+        hipLaunchKernelGGL(trace_kernel<false>, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
     return hipGetLastError();
 }
 
