@@ -121,7 +121,7 @@ typedef struct {
     uint32_t blocks_per_cu;     /* work-groups per compute unit of the persistent grid (capped by what LDS and 32 waves per CU let reside) */
     uint32_t lds_cache_nodes;   /* first N pool nodes (the top levels, breadth-first) kept in LDS */
     uint32_t refill_lanes;      /* 0 or 64: a wave takes 64-ray tiles; 1..63: claim new rays once that many lanes are idle */
-    uint32_t step_limit;        /* node steps per ray before SVO_STEP_LIMIT */
+    uint32_t step_limit;        /* cell advances plus candidate selections per ray before SVO_STEP_LIMIT */
     uint32_t claim_tiles;       /* 64-ray tiles a wave takes from the work queue at once (0: 2; at most 64) */
     uint32_t reserved[2];
 } svo_config;

@@ -293,7 +293,14 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
     uint32_t bbase = 0, bsp = 0, leaf_i = 0, leaf_end = 0;   // hierarchy walk over the candidates
     float wix = 0.f, wiy = 0.f, wiz = 0.f;                   // inverse world direction
     FrameRay fr{};
-    uint32_t cur_f = 0, pmask = 0, pchild = 0, px = 0, py = 0, pz = 0, size = 1, lvl = 1, sbase = 0, nest = 0;
+    uint32_t cur_f = 0, pmask = 0, pchild = 0, px = 0, py = 0, pz = 0, size = 1, nest = 0;
+    // stack slots: the current frame's levels start at sbase; slot = sbase +
+    // level of the current cell, top = sbase + K (so size = 2^(top - slot)).
+    // Slot s holds the child start and mask of the node at level s - 1 on
+    // the current path: pchild and pmask are always a copy of the current
+    // slot, so leaving cells up to any level is a plain read.
+    uint32_t slot = 1, sbase = 0, top = 0;
+    uint32_t lds_last = 0;  // the last cached node index (0 with no cache: reads stay in bounds)
     float tc0 = 0.f;
     int eaxis = 3;
     bool resume = false;
@@ -325,8 +332,11 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
         cur_f = f;
         pmask = F.info & FR_MASK;
         pchild = F.child;
-        lvl = 1;
         sbase = 0;
+        slot = 1;
+        top = fr.K;
+        stkc[slot * 64] = pchild;
+        stkm[slot * 64] = (uint8_t)pmask;
         nest = 0;
         size = 1u << (fr.K - 1);
         px = (fmaf((float)size, fr.ix, fr.bx) <= t0) ? size : 0u;
@@ -482,6 +492,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     ri = gidx - J.ray_begin;
                     nodes = J.nodes;
                     n_lds = min(J.lds_nodes, fill_nodes);
+                    lds_last = n_lds ? n_lds - 1u : 0u;
                     fbase = J.frame_base;
                     cbase = J.cand_base;
                     ncand = J.n_cand;
@@ -548,25 +559,26 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
             // when the ray leaves the frame's root cell or passes tl.
             auto advance = [&](float ex, float ey, float ez, float tc1) -> uint32_t {
                 const bool sx = ex == tc1, sy = ey == tc1, sz = ez == tc1;
-                if (tc1 > tl) return EV_END;
                 const uint32_t nx = px + (sx ? size : 0u);
                 const uint32_t ny = py + (sy ? size : 0u);
                 const uint32_t nz = pz + (sz ? size : 0u);
+                // the new cell's size is 2^h, h the highest changed corner bit;
+                // no plane at tc1 (a NaN) leaves diff = 0 and h = 2^32 - 1
                 const uint32_t diff = (nx ^ px) | (ny ^ py) | (nz ^ pz);
-                // no plane at tc1 (a NaN) leaves diff = 0, h = 2^32 - 1: the walk ends
                 const uint32_t h = 31u - __clz(diff);
-                if (h >= fr.K) return EV_END;  // left the frame's root cell
+                // descents between two advances are bounded by the depth, so
+                // counting advances bounds the walk
+                ++steps;
+                const uint32_t ev = (tc1 > tl || h >= fr.K) ? EV_END : (steps > a.step_limit ? EV_LIMIT : EV_NONE);
+                if (ev != EV_NONE) return ev;
                 const uint32_t nsize = 1u << h;
                 const uint32_t keep = ~(nsize - 1u);
                 px = nx & keep;
                 py = ny & keep;
                 pz = nz & keep;
-                const uint32_t nlvl = fr.K - h;
-                if (nlvl < lvl) {
-                    pchild = stkc[(sbase + nlvl) * 64];
-                    pmask = stkm[(sbase + nlvl) * 64];
-                }
-                lvl = nlvl;
+                slot = top - h;  // at or above the current level
+                pchild = stkc[slot * 64];
+                pmask = stkm[slot * 64];
                 size = nsize;
                 tc0 = tc1;
                 eaxis = sx ? 0 : (sy ? 1 : 2);   // the lowest axis crossed
@@ -585,16 +597,12 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
             }
             // the hot loop: visit, descend or advance until something happens
             while (ev == EV_NONE) {
-                if (++steps > a.step_limit) {
-                    ev = EV_LIMIT;
-                    break;
-                }
                 const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
                 const float ey = fmaf((float)(py + size), fr.iy, fr.by);
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
                 const float tc1 = min3f(ex, ey, ez);
                 // the cell's octant in its parent: bit h of each corner (size = 2^h)
-                const uint32_t h = fr.K - lvl;
+                const uint32_t h = top - slot;
                 const uint32_t oct = (__builtin_amdgcn_ubfe(px, h, 1) | (__builtin_amdgcn_ubfe(py, h, 1) << 1) |
                                       (__builtin_amdgcn_ubfe(pz, h, 1) << 2)) ^ fr.flip;
                 if (__builtin_amdgcn_ubfe(pmask, oct, 1)) {
@@ -607,8 +615,8 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     const uint32_t cz = pz + ((fmaf((float)(pz + hs), fr.iz, fr.bz) <= tc0) ? hs : 0u);
                     // separate LDS and global reads (a select between the two
                     // would become one generic load waiting on both counters)
-                    uint64_t wl = 0, wg = 0;
-                    if (n_lds) wl = lds_nodes[min(cidx, n_lds - 1u)];
+                    const uint64_t wl = lds_nodes[min(cidx, lds_last)];
+                    uint64_t wg = 0;
                     if (cidx >= n_lds) wg = gld(nodes, cidx);
                     const uint64_t w = (cidx < n_lds) ? wl : wg;
                     const uint32_t w0 = (uint32_t)w;
@@ -620,12 +628,12 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                         break;
                     }
                     if (!(w1 & kXform)) {
-                        stkc[(sbase + lvl) * 64] = pchild;
-                        stkm[(sbase + lvl) * 64] = (uint8_t)pmask;
                         const uint32_t c24 = w0 >> 8;
                         pchild = (c24 == 0xFFFFFFu) ? w1 : cidx + c24;
                         pmask = cm;
-                        ++lvl;
+                        ++slot;
+                        stkc[slot * 64] = pchild;
+                        stkm[slot * 64] = (uint8_t)pmask;
                         size = hs;
                         px = cx;
                         py = cy;
@@ -657,17 +665,20 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                 float t0;
                 int ea;
                 if (frame_setup(C, r, fminf(tl, xf_tc1), cfr, t0, ea)) {
-                    // save where the enclosing walk stands, then enter in place
-                    stkc[(sbase + lvl) * 64] = pchild;
-                    stkm[(sbase + lvl) * 64] = (uint8_t)pmask;
-                    fst[nest * 64] = make_uint4(cur_f | (lvl << 11) | (sbase << 16) | ((uint32_t)eaxis << 23), px, py, pz);
+                    // save where the enclosing walk stands (its current slot
+                    // keeps its node), then enter in place
+                    fst[nest * 64] =
+                        make_uint4(cur_f | ((slot - sbase) << 11) | (sbase << 16) | ((uint32_t)eaxis << 23), px, py, pz);
                     ++nest;
-                    sbase += lvl;
+                    sbase = slot;
                     cur_f = xf;
                     fr = cfr;
                     pmask = C.info & FR_MASK;
                     pchild = C.child;
-                    lvl = 1;
+                    slot = sbase + 1u;
+                    top = sbase + fr.K;
+                    stkc[slot * 64] = pchild;
+                    stkm[slot * 64] = (uint8_t)pmask;
                     size = 1u << (fr.K - 1);
                     px = (fmaf((float)size, fr.ix, fr.bx) <= t0) ? size : 0u;
                     py = (fmaf((float)size, fr.iy, fr.by) <= t0) ? size : 0u;
@@ -683,8 +694,9 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     --nest;
                     const uint4 e = fst[nest * 64];
                     cur_f = e.x & 0x7FFu;
-                    lvl = (e.x >> 11) & 31u;
+                    const uint32_t lvl = (e.x >> 11) & 31u;
                     sbase = (e.x >> 16) & 127u;
+                    slot = sbase + lvl;
                     eaxis = (int)((e.x >> 23) & 3u);
                     px = e.y;
                     py = e.z;
@@ -693,8 +705,9 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     int ea;
                     frame_setup(lds_frames[cur_f], r, tl, fr, t0, ea);
                     size = 1u << (fr.K - lvl);
-                    pchild = stkc[(sbase + lvl) * 64];
-                    pmask = stkm[(sbase + lvl) * 64];
+                    top = sbase + fr.K;
+                    pchild = stkc[slot * 64];
+                    pmask = stkm[slot * 64];
                     resume = true;
                 } else {
                     mode = M_SELECT;
