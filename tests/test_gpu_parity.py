@@ -355,6 +355,48 @@ def test_results_independent_of_kernel_config(ctx, torch_dev):
         ctx.free_scene(h)
 
 
+def test_step_limit(ctx, torch_dev):
+    """A ray whose walk needs more advances than step_limit reports
+    SVO_STEP_LIMIT (no slot, t = +inf, zero normal); every other ray is
+    exactly the unlimited result, and a larger limit caps a subset of the
+    rays a smaller one caps (the walk is the same up to the cap)."""
+    from paper_1911_06001_amd import svo
+    torch = torch_dev
+    cases = [(S.fbm_terrain_d10(), 9), (S.tiny_scene(3, K=6, n_slots=4, nested=True, scale_range=(0.6, 1.0)), 2)]
+    base_cfg = ctx.get_config().as_dict()
+    for sc, frame in cases:
+        if sc.name == "terrain1024":
+            rays, _ = sc.rays(W=320, H=180)
+        else:
+            rays = S.random_rays(3, 20000, 0.0, 64.0)
+        r = torch.from_numpy(rays).cuda()
+        h = ctx.upload_scene(sc)
+        try:
+            ctx.set_transforms(h, sc.xform(frame))
+            full = ctx.trace(h, r)
+            prev = None
+            for limit in (2, 8, 32):
+                ctx.set_config(step_limit=limit)
+                o = ctx.trace(h, r)
+                torch.cuda.synchronize()
+                cap = o.id == (svo.STEP_LIMIT - (1 << 32))     # int32 view of the id
+                keep = ~cap
+                _say(sc.name, "step limit", limit, "capped", int(cap.sum()), "of", rays.shape[0])
+                assert torch.all(o.inst[cap] == -1) and torch.all(torch.isinf(o.t[cap]))
+                assert torch.all(o.normal[cap] == 0)
+                for k in ("id", "inst", "t", "normal"):
+                    assert torch.equal(getattr(o, k)[keep], getattr(full, k)[keep]), (limit, k)
+                if prev is not None:
+                    assert not torch.any(cap & ~prev)
+                prev = cap
+                if limit == 2:
+                    assert int(cap.sum()) > 0
+            assert int((~prev).sum()) > 0
+        finally:
+            ctx.set_config(**base_cfg)
+            ctx.free_scene(h)
+
+
 def _corner_rays(sc, fwd, per_slot=48, seed=0):
     """Rays through points just inside the leaf corners nearest each moved
     root cell's bounding sphere, in directions perpendicular to the radius:
