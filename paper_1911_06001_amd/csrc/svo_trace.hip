@@ -145,6 +145,15 @@ __device__ __forceinline__ float box_entry(const BvhNode& B, const Ray& r, float
     return (t0 <= t1) ? t0 : INFINITY;
 }
 
+// Inverse world direction for the hierarchy's box tests, tiny components
+// clamped as in frame_setup (so no 0 * inf).
+__device__ __forceinline__ void inv_world_dir(const Ray& r, float& ix, float& iy, float& iz) {
+    const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
+    ix = rcp_fast(fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
+    iy = rcp_fast(fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
+    iz = rcp_fast(fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
+}
+
 __device__ __forceinline__ bool ray_valid(const Ray& r) {
     const bool fin = isfinite(r.ox) && isfinite(r.oy) && isfinite(r.oz) && isfinite(r.dx) && isfinite(r.dy) &&
                      isfinite(r.dz);
@@ -290,8 +299,10 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
     uint32_t best_id = kNone, best_inst = kNone;
     int best_f = -1, best_axis = 3;
     uint32_t steps = 0;
-    uint32_t bbase = 0, bsp = 0, leaf_i = 0, leaf_end = 0;   // hierarchy walk over the candidates
-    float wix = 0.f, wiy = 0.f, wiz = 0.f;                   // inverse world direction
+    // the hierarchy walk over the candidates, packed (a job has at most 1023
+    // candidates): bits 0-10 next item of the current leaf, 11-21 the
+    // leaf's end, 22-31 stack depth
+    uint32_t bws = 0;
     FrameRay fr{};
     uint32_t cur_f = 0, pmask = 0, pchild = 0, px = 0, py = 0, pz = 0, size = 1, nest = 0;
     // stack slots: the current frame's levels start at sbase; slot = sbase +
@@ -382,10 +393,9 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
             return true;
         }
         // any candidate box in front of the previous hit?
-        const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
-        const float ix = rcp_fast(fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
-        const float iy = rcp_fast(fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
-        const float iz = rcp_fast(fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
+        float ix, iy, iz;
+        inv_world_dir(r, ix, iy, iz);
+        const uint32_t bbase = J.bvh_base;
         uint32_t sp = 0;
         if (box_entry(lds_bvh[bbase], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(0u, 0u);
         while (sp > 0u) {
@@ -496,7 +506,6 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     fbase = J.frame_base;
                     cbase = J.cand_base;
                     ncand = J.n_cand;
-                    bbase = J.bvh_base;
                     const v4f* rp = reinterpret_cast<const v4f*>(J.rays);
                     const v4f r0 = gld(rp, 2 * ri);
                     const v4f r1 = gld(rp, 2 * ri + 1);
@@ -507,9 +516,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                     best_f = -1;
                     best_axis = 3;
                     steps = 0;
-                    bsp = 0;
-                    leaf_i = 0;
-                    leaf_end = 0;
+                    bws = 0;
                     bool keep = false;
                     if (a.reuse && ray_valid(r)) keep = previous_stands();
                     if (keep) {
@@ -532,15 +539,12 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                                 ent[c * 64] = e;
                             }
                         } else if (ncand) {
-                            // tiny components clamped as in frame_setup, so no 0 * inf
-                            const float eps = max3f(fabsf(r.dx), fabsf(r.dy), fabsf(r.dz)) * 0x1p-21f;
-                            wix = rcp_fast(fabsf(r.dx) < eps ? copysignf(eps, r.dx) : r.dx);
-                            wiy = rcp_fast(fabsf(r.dy) < eps ? copysignf(eps, r.dy) : r.dy);
-                            wiz = rcp_fast(fabsf(r.dz) < eps ? copysignf(eps, r.dz) : r.dz);
-                            const float e = box_entry(lds_bvh[bbase], r, wix, wiy, wiz, tl);
+                            float wix, wiy, wiz;
+                            inv_world_dir(r, wix, wiy, wiz);
+                            const float e = box_entry(lds_bvh[J.bvh_base], r, wix, wiy, wiz, tl);
                             if (e < INFINITY) {
                                 bst[0] = make_uint2(0u, __float_as_uint(e));
-                                bsp = 1;
+                                bws = 1u << 22;
                             }
                         }
                         mode = start_frame(fbase) ? M_WALK : M_SELECT;
@@ -715,6 +719,19 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
             }
         }
         if (mode == M_SELECT) {
+            // the walk's state is dead here (start_frame sets all of it before
+            // the next walk step); saying so frees its registers for the
+            // candidate search
+            fr = FrameRay{};
+            px = py = pz = 0;
+            size = 1;
+            pchild = pmask = 0;
+            slot = 1;
+            sbase = top = 0;
+            cur_f = nest = 0;
+            tc0 = 0.f;
+            eaxis = 3;
+            resume = false;
             if (++steps > a.step_limit) {
                 best_id = kStepLimitId;
                 finish();
@@ -744,6 +761,10 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                 // boxes, nearer child first, each box skipped once its entry
                 // lies beyond the best hit; a leaf's candidates then pass the
                 // sphere test (Sec. 4.1) before their exact root-cell entry
+                const uint32_t bbase = lds_jobs[job].bvh_base;
+                float wix, wiy, wiz;
+                inv_world_dir(r, wix, wiy, wiz);
+                uint32_t leaf_i = bws & 0x7FFu, leaf_end = (bws >> 11) & 0x7FFu, bsp = bws >> 22;
                 bool started = false;
                 while (!started) {
                     if (leaf_i < leaf_end) {
@@ -776,6 +797,7 @@ __global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
                         ++bsp;
                     }
                 }
+                bws = leaf_i | (leaf_end << 11) | (bsp << 22);
                 if (started) {
                     mode = M_WALK;
                 } else {
