@@ -115,7 +115,10 @@ typedef struct {
 } svo_scene_stats;
 
 /* Kernel configuration; svo_tune() picks one, svo_set_config() sets one.
-   Zero fields select the library defaults. */
+   Zero fields select the library defaults.  A launch whose tables do not
+   fit the device's LDS per work-group under it halves lds_cache_nodes, then
+   lowers waves_per_block (to a multiple of 4, then by one), before it
+   reports SVO_ERANGE; results never depend on the configuration. */
 typedef struct {
     uint32_t waves_per_block;   /* 1..16 wavefronts (64 lanes) per work-group */
     uint32_t blocks_per_cu;     /* work-groups per compute unit of the persistent grid (capped by what LDS and 32 waves per CU let reside) */
@@ -284,7 +287,8 @@ typedef struct {
    size and a private work queue (zeroed; synchronous).  Errors: SVO_EINVAL
    (NULL argument, unknown scene, non-zero reserved field), SVO_ERANGE
    (limits out of range, or the plan's LDS footprint exceeds the device's
-   even with no node cache), SVO_ENOMEM, SVO_EDEVICE.  *out is NULL on
+   even with no node cache and one wave per work-group), SVO_ENOMEM,
+   SVO_EDEVICE.  *out is NULL on
    failure. */
 int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, const svo_plan_limits* limits,
                     svo_plan** out);

@@ -367,7 +367,7 @@ namespace {
 svo_config default_config() {
     svo_config c{};
     c.waves_per_block = 8;
-    c.blocks_per_cu = 2;
+    c.blocks_per_cu = 3;   // 24 waves per CU: what the sorted-candidate kernel's registers allow
     c.lds_cache_nodes = 1024;
     c.refill_lanes = 48;
     c.step_limit = 1u << 20;
@@ -935,14 +935,29 @@ uint64_t tile_stride(uint64_t tiles) {
     return s ? s : 1;
 }
 
-// Size LDS (shrinking the node cache if needed) and launch.
-int launch(svo_ctx* ctx, const svo_config& c, svo::TraceArgs& a, hipStream_t st) {
-    a.tile_stride = tile_stride((a.n_rays + 63) / 64);
-    size_t lds = svo::trace_lds_bytes(a, c.waves_per_block);
+// Fit a launch into the per-work-group LDS limit: halve the node cache,
+// then take waves out of the work-group (to the next multiple of 4, so the
+// four SIMDs stay evenly loaded, then one at a time).  Results never depend
+// on either; a configuration tuned on one scene may meet a batch whose
+// tables are larger.  Returns the LDS bytes, above the limit if nothing fits.
+size_t fit_lds(const svo_ctx* ctx, svo::TraceArgs& a, uint32_t& waves) {
+    size_t lds = svo::trace_lds_bytes(a, waves);
     while (lds > ctx->max_lds && a.lds_nodes > 0) {
         a.lds_nodes = (a.lds_nodes / 2) & ~1u;
-        lds = svo::trace_lds_bytes(a, c.waves_per_block);
+        lds = svo::trace_lds_bytes(a, waves);
     }
+    while (lds > ctx->max_lds && waves > 1) {
+        waves = (waves > 4 && waves % 4) ? waves & ~3u : (waves > 4 ? waves - 4 : waves - 1);
+        lds = svo::trace_lds_bytes(a, waves);
+    }
+    return lds;
+}
+
+// Size LDS (see fit_lds) and launch.
+int launch(svo_ctx* ctx, const svo_config& cfg, svo::TraceArgs& a, hipStream_t st) {
+    a.tile_stride = tile_stride((a.n_rays + 63) / 64);
+    svo_config c = cfg;
+    const size_t lds = fit_lds(ctx, a, c.waves_per_block);
     if (lds > ctx->max_lds) return fail(SVO_ERANGE, "launch needs %zu bytes of LDS per work-group", lds);
     if (!a.jobs && a.job0.lds_nodes) a.job0.lds_nodes = a.lds_nodes;
     svo::LaunchCfg L{};
@@ -1285,11 +1300,7 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         a.nest_levels = pl->nest_cap;
         a.lds_nodes = (uint32_t)std::min<uint64_t>(pl->cfg.lds_cache_nodes, max_pool) & ~1u;
         fill_common(pl->cfg, a);
-        size_t lds = svo::trace_lds_bytes(a, pl->cfg.waves_per_block);
-        while (lds > ctx->max_lds && a.lds_nodes > 0) {
-            a.lds_nodes = (a.lds_nodes / 2) & ~1u;
-            lds = svo::trace_lds_bytes(a, pl->cfg.waves_per_block);
-        }
+        const size_t lds = fit_lds(ctx, a, pl->cfg.waves_per_block);
         if (lds > ctx->max_lds) return fail(SVO_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
         pl->launch_cfg.waves_per_block = pl->cfg.waves_per_block;
         pl->launch_cfg.blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ctx->n_cu * resident_blocks(ctx, pl->cfg, lds));
@@ -1427,7 +1438,7 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     // Two stages: the launch shape (waves per work-group, work-groups per
     // CU, LDS node cache) at whole-tile refill and 2-tile claims, then
     // refill and claim size for the winning shape.
-    static const uint32_t kWaves[] = {4, 8, 16};
+    static const uint32_t kWaves[] = {4, 8, 12, 16};
     static const uint32_t kBlocks[] = {1, 2, 3, 4, 5, 6, 8};
     static const uint32_t kCache[] = {1024, 2048, 4096};
     static const uint32_t kRefill[] = {0, 48};

@@ -196,9 +196,14 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
 // kSorted: every job's candidates go through the per-lane entry table (at
 // most 16 of them); otherwise through the per-frame box hierarchy.  A launch
 // uses one of the two, and each instantiation carries only its own path,
-// which keeps the sorted one at fewer registers (more resident waves).
+// which keeps the sorted one at fewer registers.  The sorted one is compiled
+// for 6 resident waves per SIMD (80 VGPRs): the few values that then go to
+// scratch are per-ray state outside the walk loop, and the extra waves hide
+// more of the node-load latency.  The hierarchy one keeps its natural 104
+// VGPRs (4 waves): forcing it lower spills inside its candidate search.
 template <bool kSorted>
-__global__ __launch_bounds__(1024) void trace_kernel(TraceArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 6 : 1, 8))) void trace_kernel(
+    TraceArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* p = smem;
     uint64_t* lds_nodes = reinterpret_cast<uint64_t*>(p);

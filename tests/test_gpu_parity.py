@@ -112,8 +112,10 @@ def test_terrain1024_reduced_frames(ctx, torch_dev):
 
 
 def test_terrain1024_full_resolution_sampled(ctx, torch_dev):
-    """1920x1080 in the benchmark's launch: every 17th ray plus one 64x64 tile
-    block of rays are checked against the oracle one by one."""
+    """1920x1080 in the benchmark's launch (the configuration the autotuner
+    picks for these rays, as the benchmark does): every 17th ray plus one
+    block of 4096 consecutive rays are checked against the oracle one by one,
+    and the default configuration gives the same results bit for bit."""
     sc = S.fbm_terrain_d10()
     rays, pix = sc.rays()
     n = rays.shape[0]
@@ -121,9 +123,14 @@ def test_terrain1024_full_resolution_sampled(ctx, torch_dev):
     h = ctx.upload_scene(sc)
     try:
         ctx.set_transforms(h, sc.xform(30))
+        g0 = _trace(ctx, torch_dev, h, rays)
+        cfg = ctx.tune(h, torch_dev.from_numpy(rays).cuda())
+        _say("tuned", cfg.as_dict())
         g = _trace(ctx, torch_dev, h, rays)
     finally:
         ctx.free_scene(h)
+    for a, b in zip(g0, g):
+        assert np.array_equal(a, b)
     ref = oracle.trace_scene(sc, rays[idx], frame=30, margin=True)
     st = parity.compare(tuple(a[idx] for a in g), ref, ref.margin, rays[idx])
     _say("terrain1024-1080p-sampled", st)
@@ -488,7 +495,24 @@ def test_hierarchy_over_many_candidates(ctx, torch_dev, n_slots):
         plan.launch()
         torch.cuda.synchronize()
         plan.close()
-        for got in (jobs[1], pj[1]):
+        # a configuration too large for these tables' LDS: the launch drops
+        # the node cache and waves per work-group until it fits
+        base_cfg = ctx.get_config().as_dict()
+        try:
+            ctx.set_config(waves_per_block=16, blocks_per_cu=2, lds_cache_nodes=4096)
+            big = [dict(scene=hs, rays=rs, **_outs(torch, rs.shape[0])), dict(scene=h, rays=r, **_outs(torch, r.shape[0]))]
+            ctx.trace_batch(big)
+            # 800 frame records: with 16 (and 12) waves the plan's tables
+            # exceed the LDS even without a node cache, so it drops to 8
+            plan16 = ctx.plan([h, hs], max_jobs=4, max_frames=800)
+            pj16 = [dict(scene=hs, rays=rs, **_outs(torch, rs.shape[0])), dict(scene=h, rays=r, **_outs(torch, r.shape[0]))]
+            plan16.set_jobs(pj16)
+            plan16.launch()
+            torch.cuda.synchronize()
+            plan16.close()
+        finally:
+            ctx.set_config(**base_cfg)
+        for got in (jobs[1], pj[1], big[1], pj16[1]):
             assert torch.equal(got["out_id"], alone.id) and torch.equal(got["out_t"], alone.t)
             assert torch.equal(got["out_inst"], alone.inst) and torch.equal(got["out_normal"], alone.normal)
     finally:

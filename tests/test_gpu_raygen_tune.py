@@ -84,7 +84,10 @@ def test_tune_picks_a_config_and_keeps_results(ctx, torch_dev):
         torch.cuda.synchronize()
         cfg = ctx.tune(h, r)
         _say("tuned", cfg.as_dict())
-        assert 1 <= cfg.waves_per_block <= 8 and 1 <= cfg.blocks_per_cu <= 32
+        # one of the tuner's candidates (svo_tune's search space)
+        assert cfg.waves_per_block in (4, 8, 12, 16) and cfg.blocks_per_cu in (1, 2, 3, 4, 5, 6, 8)
+        assert cfg.waves_per_block * cfg.blocks_per_cu <= 32
+        assert cfg.lds_cache_nodes in (1024, 2048, 4096) and cfg.refill_lanes in (0, 48) and cfg.claim_tiles in (1, 2, 4)
         after = ctx.trace(h, r)
         torch.cuda.synchronize()
         assert torch.equal(before.id, after.id) and torch.equal(before.t, after.t)
