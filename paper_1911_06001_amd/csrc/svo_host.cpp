@@ -1183,7 +1183,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
                 cache_pool_nodes = J.S->n_nodes;
                 if (J.S->tuned) pcfg = &J.S->cfg;
             }
-        const svo_config& cfg = *pcfg;
+        svo_config cfg = *pcfg;
 
         // pack [jobs][frames][candidates][spheres][hierarchy nodes]
         const size_t jb = P.jobs.size() * sizeof(svo::JobRec);
@@ -1207,11 +1207,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         a.nest_levels = P.nest_levels;
         fill_common(cfg, a);
         // size LDS now: a smaller node cache changes the jobs' lds_nodes
-        size_t lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
-        while (lds > ctx->max_lds && a.lds_nodes > 0) {
-            a.lds_nodes = (a.lds_nodes / 2) & ~1u;
-            lds = svo::trace_lds_bytes(a, cfg.waves_per_block);
-        }
+        const size_t lds = fit_lds(ctx, a, cfg.waves_per_block);
         if (lds > ctx->max_lds) return fail(SVO_ERANGE, "batch needs %zu bytes of LDS per work-group", lds);
 
         auto& B = ctx->batch[ctx->next_batch];

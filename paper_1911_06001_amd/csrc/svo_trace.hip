@@ -182,7 +182,7 @@ __device__ __forceinline__ void gst(T* p, uint64_t i, T v) {
 // Per-lane candidate state in LDS: the entry table (sorted path) or the
 // hierarchy stack of (node, entry t) pairs, one more than its levels.
 __host__ __device__ __forceinline__ size_t cand_lane_bytes(const TraceArgs& a) {
-    return a.sort_cand ? (size_t)a.max_cand * 4 : (a.max_cand ? (size_t)(a.bvh_depth + 1) * 8 : 0);
+    return a.sort_cand ? (size_t)a.max_cand * 4 : (a.max_cand ? (size_t)(a.bvh_depth + 1) * 4 : 0);
 }
 
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
@@ -225,7 +225,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     const uint32_t bst_cap = a.bvh_depth + 1;
     unsigned char* wp = p + per_wave * wave;
     float* ent = reinterpret_cast<float*>(wp) + lane;                                   // candidate c at ent[c * 64]
-    uint2* bst = reinterpret_cast<uint2*>(wp) + lane;                                   // hierarchy entry k at bst[k * 64]
+    // hierarchy stack entry k at bst[k * 64]: a box index; its entry is tested
+    // again when popped, against the best hit by then
+    uint32_t* bst = reinterpret_cast<uint32_t*>(wp) + lane;
     // traversal stack, level l: child start at stkc[l * 64], child mask at stkm[l * 64]
     uint32_t* stkc = reinterpret_cast<uint32_t*>(wp + ent_bytes) + lane;
     uint8_t* stkm = reinterpret_cast<uint8_t*>(wp + ent_bytes + (size_t)a.stack_levels * 256) + lane;
@@ -402,17 +404,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         inv_world_dir(r, ix, iy, iz);
         const uint32_t bbase = J.bvh_base;
         uint32_t sp = 0;
-        if (box_entry(lds_bvh[bbase], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(0u, 0u);
+        if (box_entry(lds_bvh[bbase], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = 0u;
         while (sp > 0u) {
-            const BvhNode& N = lds_bvh[bbase + bst[(--sp) * 64].x];
+            const BvhNode& N = lds_bvh[bbase + bst[(--sp) * 64]];
             if (N.b & kBvhLeaf) {
                 for (uint32_t c = N.a; c < N.a + (N.b & 0xFFFFu); ++c)
                     if (may_reach(lds_cand[cbase + c], tlim)) return false;
                 continue;
             }
             if (sp + 2u > bst_cap) return false;   // cannot happen (depth bound); trace it then
-            if (box_entry(lds_bvh[bbase + N.a], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(N.a, 0u);
-            if (box_entry(lds_bvh[bbase + N.b], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = make_uint2(N.b, 0u);
+            if (box_entry(lds_bvh[bbase + N.a], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = N.a;
+            if (box_entry(lds_bvh[bbase + N.b], r, ix, iy, iz, tlim) < INFINITY) bst[(sp++) * 64] = N.b;
         }
         return true;
     };
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                             inv_world_dir(r, wix, wiy, wiz);
                             const float e = box_entry(lds_bvh[J.bvh_base], r, wix, wiy, wiz, tl);
                             if (e < INFINITY) {
-                                bst[0] = make_uint2(0u, __float_as_uint(e));
+                                bst[0] = 0u;
                                 bws = 1u << 22;
                             }
                         }
@@ -779,9 +781,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     }
                     if (bsp == 0u) break;
                     --bsp;
-                    const uint2 e = bst[bsp * 64];
-                    if (__uint_as_float(e.y) > tl) continue;
-                    const BvhNode& N = lds_bvh[bbase + e.x];
+                    // the box may now lie beyond the best hit
+                    const BvhNode& N = lds_bvh[bbase + bst[bsp * 64]];
+                    if (!(box_entry(N, r, wix, wiy, wiz, tl) < INFINITY)) continue;
                     if (N.b & kBvhLeaf) {
                         leaf_i = N.a;
                         leaf_end = N.a + (N.b & 0xFFFFu);
@@ -794,11 +796,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     const uint32_t nn = left_near ? N.a : N.b, nf = left_near ? N.b : N.a;
                     // the far child first, so the near one is popped next
                     if (ef < INFINITY && bsp < bst_cap) {
-                        bst[bsp * 64] = make_uint2(nf, __float_as_uint(ef));
+                        bst[bsp * 64] = nf;
                         ++bsp;
                     }
                     if (en < INFINITY && bsp < bst_cap) {
-                        bst[bsp * 64] = make_uint2(nn, __float_as_uint(en));
+                        bst[bsp * 64] = nn;
                         ++bsp;
                     }
                 }
