@@ -201,7 +201,10 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
 // scratch are per-ray state outside the walk loop, and the extra waves hide
 // more of the node-load latency.  The hierarchy one keeps its natural 104
 // VGPRs (4 waves): forcing it lower spills inside its candidate search.
-template <bool kSorted>
+// kSingle: a one-job launch (the job in the arguments), whose pool, cache
+// size and table offsets are then launch-wide values (scalar registers)
+// rather than per-lane ones.
+template <bool kSorted, bool kSingle>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 6 : 1, 8))) void trace_kernel(
     TraceArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -297,10 +300,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
 
     // per-lane state
     uint32_t mode = M_DONE;
-    uint64_t ri = 0;           // ray index within its job
+    uint32_t ri = 0;           // ray index within its job (a launch holds at most 0xff000000 rays)
     uint32_t job = 0;
-    const uint64_t* nodes = nullptr;
-    uint32_t n_lds = 0, fbase = 0, cbase = 0, ncand = 0;
+    const uint64_t* nodes = kSingle ? a.job0.nodes : nullptr;
+    uint32_t n_lds = kSingle ? min(a.job0.lds_nodes, fill_nodes) : 0u;
+    uint32_t fbase = 0, cbase = 0, ncand = kSingle ? a.job0.n_cand : 0u;
     Ray r{};
     float best_t = INFINITY, tl = 0.f;
     uint32_t best_id = kNone, best_inst = kNone;
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // the current path: pchild and pmask are always a copy of the current
     // slot, so leaving cells up to any level is a plain read.
     uint32_t slot = 1, sbase = 0, top = 0;
-    uint32_t lds_last = 0;  // the last cached node index (0 with no cache: reads stay in bounds)
+    uint32_t lds_last = n_lds ? n_lds - 1u : 0u;  // the last cached node index (0 with no cache: reads stay in bounds)
     float tc0 = 0.f;
     int eaxis = 3;
     bool resume = false;
@@ -439,9 +443,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         if (J.out_inst) gst(J.out_inst, ri, best_inst);
         gst(J.out_t, ri, best_t);
         if (J.out_n) {
-            gst(J.out_n, 3 * ri, nx);
-            gst(J.out_n, 3 * ri + 1, ny);
-            gst(J.out_n, 3 * ri + 2, nz);
+            gst(J.out_n, 3 * (uint64_t)ri, nx);
+            gst(J.out_n, 3 * (uint64_t)ri + 1, ny);
+            gst(J.out_n, 3 * (uint64_t)ri + 2, nz);
         }
         mode = M_DONE;
     };
@@ -498,24 +502,31 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 uint64_t gidx = n_rays;
                 if (rank < take && slot < n_tiles) gidx = ((slot * tstride) % n_tiles) * 64u + (j & 63u);
                 if (gidx < n_rays) {
-                    // the job holding this launch-wide ray index (jobs are in ray order)
-                    uint32_t lo = 0, hi = n_jobs;
-                    while (hi - lo > 1u) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (lds_jobs[mid].ray_begin <= gidx) lo = mid; else hi = mid;
+                    const float4* rays;
+                    if constexpr (kSingle) {
+                        ri = (uint32_t)gidx;
+                        rays = a.job0.rays;
+                    } else {
+                        // the job holding this launch-wide ray index (jobs are in ray order)
+                        uint32_t lo = 0, hi = n_jobs;
+                        while (hi - lo > 1u) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (lds_jobs[mid].ray_begin <= gidx) lo = mid; else hi = mid;
+                        }
+                        job = lo;
+                        const JobRec& J = lds_jobs[job];
+                        ri = (uint32_t)(gidx - J.ray_begin);
+                        nodes = J.nodes;
+                        n_lds = min(J.lds_nodes, fill_nodes);
+                        lds_last = n_lds ? n_lds - 1u : 0u;
+                        fbase = J.frame_base;
+                        cbase = J.cand_base;
+                        ncand = J.n_cand;
+                        rays = J.rays;
                     }
-                    job = lo;
-                    const JobRec& J = lds_jobs[job];
-                    ri = gidx - J.ray_begin;
-                    nodes = J.nodes;
-                    n_lds = min(J.lds_nodes, fill_nodes);
-                    lds_last = n_lds ? n_lds - 1u : 0u;
-                    fbase = J.frame_base;
-                    cbase = J.cand_base;
-                    ncand = J.n_cand;
-                    const v4f* rp = reinterpret_cast<const v4f*>(J.rays);
-                    const v4f r0 = gld(rp, 2 * ri);
-                    const v4f r1 = gld(rp, 2 * ri + 1);
+                    const v4f* rp = reinterpret_cast<const v4f*>(rays);
+                    const v4f r0 = gld(rp, 2 * (uint64_t)ri);
+                    const v4f r1 = gld(rp, 2 * (uint64_t)ri + 1);
                     r = Ray{r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
                     best_t = INFINITY;
                     best_id = kNone;
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                         } else if (ncand) {
                             float wix, wiy, wiz;
                             inv_world_dir(r, wix, wiy, wiz);
-                            const float e = box_entry(lds_bvh[J.bvh_base], r, wix, wiy, wiz, tl);
+                            const float e = box_entry(lds_bvh[lds_jobs[job].bvh_base], r, wix, wiy, wiz, tl);
                             if (e < INFINITY) {
                                 bst[0] = 0u;
                                 bws = 1u << 22;
@@ -830,18 +841,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
 }
 
 hipError_t prepare_trace(size_t max_lds) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel<true>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&trace_kernel<false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+    const void* kernels[] = {reinterpret_cast<const void*>(&trace_kernel<true, true>),
+                             reinterpret_cast<const void*>(&trace_kernel<true, false>),
+                             reinterpret_cast<const void*>(&trace_kernel<false, true>),
+                             reinterpret_cast<const void*>(&trace_kernel<false, false>)};
+    for (const void* k : kernels) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream) {
-    if (a.sort_cand)
-        hipLaunchKernelGGL(trace_kernel<true>, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
-    else
-        hipLaunchKernelGGL(trace_kernel<false>, dim3(c.blocks), dim3(c.waves_per_block * 64), c.lds_bytes, stream, a);
+    const dim3 grid(c.blocks), block(c.waves_per_block * 64);
+    if (a.sort_cand) {
+        if (!a.jobs)
+            hipLaunchKernelGGL((trace_kernel<true, true>), grid, block, c.lds_bytes, stream, a);
+        else
+            hipLaunchKernelGGL((trace_kernel<true, false>), grid, block, c.lds_bytes, stream, a);
+    } else {
+        if (!a.jobs)
+            hipLaunchKernelGGL((trace_kernel<false, true>), grid, block, c.lds_bytes, stream, a);
+        else
+            hipLaunchKernelGGL((trace_kernel<false, false>), grid, block, c.lds_bytes, stream, a);
+    }
     return hipGetLastError();
 }
 
