@@ -1229,6 +1229,12 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
                      reinterpret_cast<uint32_t*>(B.host + jb + fb), reinterpret_cast<float*>(B.host + sb),
                      reinterpret_cast<svo::BvhNode*>(B.host + bb), a.lds_nodes);
         a.jobs = reinterpret_cast<const svo::JobRec*>(B.dev);
+        if (P.jobs.size() == 1) {
+            // one job: passed in the arguments, which selects the single-job
+            // kernel (the job's pool and table offsets launch-wide)
+            a.job0 = *reinterpret_cast<const svo::JobRec*>(B.host);
+            a.jobs = nullptr;
+        }
         a.frames = reinterpret_cast<const svo::FrameRec*>(B.dev + jb);
         a.cand = reinterpret_cast<const uint32_t*>(B.dev + jb + fb);
         a.spheres = reinterpret_cast<const float4*>(B.dev + sb);

@@ -304,7 +304,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     uint32_t job = 0;
     const uint64_t* nodes = kSingle ? a.job0.nodes : nullptr;
     uint32_t n_lds = kSingle ? min(a.job0.lds_nodes, fill_nodes) : 0u;
-    uint32_t fbase = 0, cbase = 0, ncand = kSingle ? a.job0.n_cand : 0u;
+    uint32_t fbase = kSingle ? a.job0.frame_base : 0u, cbase = kSingle ? a.job0.cand_base : 0u;
+    uint32_t ncand = kSingle ? a.job0.n_cand : 0u;
     Ray r{};
     float best_t = INFINITY, tl = 0.f;
     uint32_t best_id = kNone, best_inst = kNone;
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 if (gidx < n_rays) {
                     const float4* rays;
                     if constexpr (kSingle) {
-                        ri = (uint32_t)gidx;
+                        ri = (uint32_t)(gidx - a.job0.ray_begin);
                         rays = a.job0.rays;
                     } else {
                         // the job holding this launch-wide ray index (jobs are in ray order)
