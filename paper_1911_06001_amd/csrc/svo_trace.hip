@@ -180,7 +180,7 @@ __device__ __forceinline__ void gst(T* p, uint64_t i, T v) {
 }  // namespace
 
 // Per-lane candidate state in LDS: the entry table (sorted path) or the
-// hierarchy stack of (node, entry t) pairs, one more than its levels.
+// hierarchy stack of box indices, one more than its levels.
 __host__ __device__ __forceinline__ size_t cand_lane_bytes(const TraceArgs& a) {
     return a.sort_cand ? (size_t)a.max_cand * 4 : (a.max_cand ? (size_t)(a.bvh_depth + 1) * 4 : 0);
 }
@@ -199,8 +199,9 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
 // which keeps the sorted one at fewer registers.  The sorted one is compiled
 // for 6 resident waves per SIMD (80 VGPRs): the few values that then go to
 // scratch are per-ray state outside the walk loop, and the extra waves hide
-// more of the node-load latency.  The hierarchy one keeps its natural 104
-// VGPRs (4 waves): forcing it lower spills inside its candidate search.
+// more of the node-load latency.  The hierarchy one keeps its natural
+// count (93 VGPRs single-job, 101 batched): forcing it lower spills inside
+// its candidate search.
 // kSingle: a one-job launch (the job in the arguments), whose pool, cache
 // size and table offsets are then launch-wide values (scalar registers)
 // rather than per-lane ones.
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // hierarchy stack entry k at bst[k * 64]: a box index; its entry is tested
     // again when popped, against the best hit by then
     uint32_t* bst = reinterpret_cast<uint32_t*>(wp) + lane;
-    // traversal stack, level l: child start at stkc[l * 64], child mask at stkm[l * 64]
+    // traversal stack, slot l: child start at stkc[l * 64], child mask at stkm[l * 64]
     uint32_t* stkc = reinterpret_cast<uint32_t*>(wp + ent_bytes) + lane;
     uint8_t* stkm = reinterpret_cast<uint8_t*>(wp + ent_bytes + (size_t)a.stack_levels * 256) + lane;
     uint4* fst = reinterpret_cast<uint4*>(wp + ent_bytes + (size_t)a.stack_levels * 320) + lane;  // nest n at fst[n * 64]
@@ -319,9 +320,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     uint32_t cur_f = 0, pmask = 0, pchild = 0, px = 0, py = 0, pz = 0, size = 1, nest = 0;
     // stack slots: the current frame's levels start at sbase; slot = sbase +
     // level of the current cell, top = sbase + K (so size = 2^(top - slot)).
-    // Slot s holds the child start and mask of the node at level s - 1 on
-    // the current path: pchild and pmask are always a copy of the current
-    // slot, so leaving cells up to any level is a plain read.
+    // Slot s holds the child start and mask of the node on the current path
+    // whose children are the cells of level s - sbase: pchild and pmask are
+    // always a copy of the current slot, so leaving cells up to any level is
+    // a plain read.
     uint32_t slot = 1, sbase = 0, top = 0;
     uint32_t lds_last = n_lds ? n_lds - 1u : 0u;  // the last cached node index (0 with no cache: reads stay in bounds)
     float tc0 = 0.f;

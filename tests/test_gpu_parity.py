@@ -296,7 +296,8 @@ def _outs(torch, n):
 
 def test_batch_equals_alone(ctx, torch_dev):
     """Rays of several requests, scenes and animation frames in one launch:
-    every job's result is bit-identical to tracing it alone."""
+    every job's result is bit-identical to tracing it alone, and to a batch
+    of that job alone."""
     torch = torch_dev
     sph = S.noisy_sphere_d6()
     ter = S.fbm_terrain_d10()
@@ -329,6 +330,13 @@ def test_batch_equals_alone(ctx, torch_dev):
             assert torch.equal(alone.inst, j["out_inst"]), name
             assert torch.equal(alone.t, j["out_t"]), name
             assert torch.equal(alone.normal, j["out_normal"]), name
+        # a batch of one job (its own transforms) runs the single-job kernel:
+        # the same results as that job in the larger batch
+        one = [dict(scene=hs["ter"], rays=jobs[2]["rays"], fwd=specs[2][2], **_outs(torch, specs[2][1].shape[0]))]
+        ctx.trace_batch(one)
+        torch.cuda.synchronize()
+        for k in ("out_id", "out_inst", "out_t", "out_normal"):
+            assert torch.equal(one[0][k], jobs[2][k]), k
         # and against the oracle for the job with its own transforms
         ref = oracle.trace_scene(ter, specs[2][1], fwd=specs[2][2], margin=True)
         g = (jobs[2]["out_id"].cpu().numpy().view(np.uint32), jobs[2]["out_inst"].cpu().numpy().view(np.uint32),
