@@ -260,7 +260,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // work-groups beyond what this launch's rays need (a plan's grid is
     // fixed) fill no LDS and claim nothing
     const uint32_t wpb = blockDim.x >> 6;
-    const bool active = (uint64_t)blockIdx.x < (((n_rays + 63) >> 6) + wpb - 1) / wpb;
+    const uint32_t n_active = (uint32_t)min((uint64_t)gridDim.x, (((n_rays + 63) >> 6) + wpb - 1) / wpb);
+    const bool active = blockIdx.x < n_active;
     if (!active) {
         fill_nodes = 0;
         n_frames = 0;
@@ -828,13 +829,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         }
     }
 
-    // the last work-group out resets the queue for the next launch
+    // the last work-group out resets the queue for the next launch; only
+    // work-groups that may claim count (an idle one of a plan's fixed grid
+    // touches no counter, and skipping its atomic spares the others a
+    // same-address queue)
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (active && threadIdx.x == 0) {
         __threadfence();
         uint32_t* fin = a.queue + kQueueFinished;
         const uint32_t prev = atomicAdd(fin, 1u);
-        if (prev == gridDim.x - 1) {
+        if (prev == n_active - 1) {
             for (uint32_t p = 0; p < kQueueParts; ++p) atomicExch(a.queue + p * kQueueStride, 0u);
             atomicExch(a.queue + kQueueDry, 0u);
             atomicExch(a.queue + kQueueDry + 1, 0u);
