@@ -116,8 +116,9 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
 // Bounding-sphere test of the paper's Sec. 4.1 (Eq. 4), made conservative
 // for FP32: false only when the ray segment [tmin, tlimit] certainly misses
 // the sphere (its perpendicular distance exceeds the radius, or the sphere
-// lies wholly before tmin or after tlimit).  The radius is inflated by a
-// relative 1e-4 plus 1e-6 of the centre distance to absorb rounding.
+// lies wholly before tmin or after tlimit).  To absorb rounding the radius
+// is inflated by a relative 1e-4, and its square by 1e-6 of the squared
+// centre distance (about 1e-3 of the distance).
 __device__ __forceinline__ bool sphere_may_hit(const float4 sp, const Ray& r, float tlimit) {
     const float lx = sp.x - r.ox, ly = sp.y - r.oy, lz = sp.z - r.oz;
     const float dd = fmaf(r.dx, r.dx, fmaf(r.dy, r.dy, r.dz * r.dz));
