@@ -141,13 +141,14 @@ def instances_throughput(ctx, steps):
     return res
 
 
-def c5_throughput(ctx, steps, frames=60):
+def c5_throughput(ctx, steps, frames=60, knobs=None):
     """Depth-12 ridged terrain (4096^3, ~1.5e8 nodes = 1.2 GB pool, 256
     animated level-4 subtrees): per frame, upload that frame's transforms,
     trace 3840x2160 primary rays, generate 2 cosine-weighted AO rays per
     pixel on the device, trace them and composite the RGBA8 frame.  Kernel times from HIP events on the
     launch stream; algorithmic bytes per ray from the oracle's counters on a
-    sample of the same rays (every 997th)."""
+    sample of the same rays (every 997th).  With ``knobs`` the kernel runs
+    that configuration instead of the autotuner's."""
     import torch
     import oracle
     from svogen import scenes
@@ -160,7 +161,11 @@ def c5_throughput(ctx, steps, frames=60):
     rays = torch.from_numpy(rays_np).cuda()
     xf = [sc.xform(f) for f in range(frames)]
     ctx.set_transforms(h, xf[0])
-    tuned = ctx.tune(h, rays).as_dict()
+    if knobs:
+        ctx.set_config(**knobs)
+        tuned = ctx.get_config().as_dict()
+    else:
+        tuned = ctx.tune(h, rays).as_dict()
     stream = torch.cuda.current_stream()
     prim = ctx.trace(h, rays)
     ao = ctx.ao_rays(rays, prim, k=2, seed=5, radius=64.0)
@@ -314,6 +319,8 @@ def main():
     ap.add_argument("--no-ceilings", action="store_true", help="skip the gather / stream ceiling kernels")
     ap.add_argument("--no-c5", action="store_true", help="skip the depth-12 terrain measurement")
     ap.add_argument("--no-hit-buffer", action="store_true", help="skip the hit-buffer (frame-to-frame reuse) run")
+    ap.add_argument("--c5-only", action="store_true",
+                    help="run only the depth-12 terrain leg (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -339,6 +346,25 @@ def main():
     from paper_1911_06001_amd import svo
     from svogen import scenes
 
+    knobs = {}
+    if args.waves_per_block:
+        knobs["waves_per_block"] = args.waves_per_block
+    if args.blocks_per_cu:
+        knobs["blocks_per_cu"] = args.blocks_per_cu
+    if args.lds_cache_nodes >= 0:
+        knobs["lds_cache_nodes"] = args.lds_cache_nodes
+    if args.refill >= 0:
+        knobs["refill_lanes"] = args.refill
+    if args.claim_tiles:
+        knobs["claim_tiles"] = args.claim_tiles
+    if args.c5_only:
+        ctx = svo.Context(0)
+        res, _, h5 = c5_throughput(ctx, args.steps, knobs=knobs or None)
+        ctx.free_scene(h5)
+        ctx.close()
+        print(json.dumps({"c5_only": res}), flush=True)
+        return
+
     t0 = time.perf_counter()
     sc = scenes.fbm_terrain_d10(frames=args.frames)
     rays_np, _ = sc.rays(W=args.width, H=args.height)
@@ -352,17 +378,6 @@ def main():
     out_t = torch.empty(n, dtype=torch.float32, device=dev)
     out_n = torch.empty((n, 3), dtype=torch.float32, device=dev)
     ctx = svo.Context(0)
-    knobs = {}
-    if args.waves_per_block:
-        knobs["waves_per_block"] = args.waves_per_block
-    if args.blocks_per_cu:
-        knobs["blocks_per_cu"] = args.blocks_per_cu
-    if args.lds_cache_nodes >= 0:
-        knobs["lds_cache_nodes"] = args.lds_cache_nodes
-    if args.refill >= 0:
-        knobs["refill_lanes"] = args.refill
-    if args.claim_tiles:
-        knobs["claim_tiles"] = args.claim_tiles
     cfg = ctx.set_config(**knobs).as_dict()
     log("kernel config", cfg)
     anim = ctx.upload_scene(sc)
