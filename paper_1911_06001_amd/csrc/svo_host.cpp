@@ -1451,7 +1451,7 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
         int r = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
         if (r) return r;  // SVO_ERANGE: does not fit in LDS
         if (hipEventRecord(e0, st) != hipSuccess) return fail(SVO_EDEVICE, "tuner event record failed");
-        for (int k = 0; k < 3 && r == SVO_OK; ++k)
+        for (int k = 0; k < 6 && r == SVO_OK; ++k)
             r = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
         if (r) return r;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
