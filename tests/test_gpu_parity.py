@@ -89,6 +89,34 @@ def test_tiny_nested(ctx, torch_dev, seed):
     _check_scene(ctx, torch_dev, sc, rays, label="tiny-%d" % seed)
 
 
+def test_random_scenes_stress(ctx, torch_dev):
+    """Many seeded random scenes: depth 4-6, 1-8 slots, nested or not,
+    shrinking to growing scales and translations (contained, leaving and
+    overlapping slots), camera-like and inside rays, some with a short tmax;
+    each against the oracle.  Rare paths (in-place frames at several depths,
+    candidates crossing each other, ties) get many chances to show up."""
+    rng = np.random.default_rng(2024)
+    cases = 0
+    for seed in range(100, 116):
+        K = int(rng.integers(4, 7))
+        slots = int(rng.integers(1, 9))
+        nested = bool(rng.integers(0, 2))
+        lo_s, hi_s = sorted(rng.uniform(0.3, 2.2, 2))
+        try:
+            sc = S.tiny_scene(seed, K=K, n_slots=slots, nested=nested, scale_range=(lo_s, hi_s),
+                              translate=float(rng.uniform(0.0, 0.5)))
+        except ValueError:
+            continue  # an empty random scene
+        rays = np.concatenate([S.random_rays(seed, 2500, 0.0, sc.root_size),
+                               S.random_rays(seed + 1000, 800, 0.0, sc.root_size, inside_frac=1.0)])
+        short = np.arange(rays.shape[0]) % 5 == 0
+        rays[short, 7] = np.float32(0.3 * sc.root_size)
+        _check_scene(ctx, torch_dev, sc, rays, label="stress-%d K%d s%d %s" % (seed, K, slots,
+                                                                              "nested" if nested else "flat"))
+        cases += 1
+    assert cases >= 12
+
+
 def test_axis_aligned_and_inside(ctx, torch_dev):
     sc = S.tiny_scene(5, K=4, n_slots=2, nested=False, rotate=False, scale_range=(1.0, 1.0), translate=0.4)
     rng = np.random.default_rng(3)
