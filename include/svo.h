@@ -178,7 +178,10 @@ int svo_get_scene_stats(svo_ctx* ctx, svo_scene scene, svo_scene_stats* out);
    compose).  The library composes and inverts in FP64 on the host, packs one
    64-byte FP32 record per frame and copies the whole table on `stream`;
    traces enqueued on `stream` afterwards see the new transforms, earlier
-   ones the old (two device tables alternate).  A slot whose moved cell stays
+   ones the old (two device tables alternate, so the second call after a
+   trace rewrites the table that trace reads: a trace on another stream must
+   have finished before then, which the caller orders; svo_trace_batch jobs
+   that pass their own maps are not affected).  A slot whose moved cell stays
    inside its static cell (with a margin of 1e-5 cell) is entered in place
    when the walk reaches it (at most SVO_MAX_INLINE_NEST deep); every other
    slot is traced as a separate candidate in order of its root-cell entry.
@@ -254,7 +257,8 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
    colour * weight over the pixel's samples, rounded half up; alpha 255.
    out_rgba: device, width * height uint32, row-major (R in the low byte).
    Errors: SVO_EINVAL (unknown scene, NULL buffer, ambient_permille > 1000),
-   SVO_ERANGE (samples 0 or > 1024, k > 64, too large), SVO_EDEVICE. */
+   SVO_ERANGE (samples 0 or > 1024, k > 64, a side above 2^20 pixels, more
+   than 0xff000000 samples), SVO_EDEVICE. */
 int svo_shade(svo_ctx* ctx, svo_scene scene, const uint32_t* prim_id, const uint32_t* ao_id, uint32_t width,
               uint32_t height, uint32_t samples, uint32_t tiled, uint32_t k, uint32_t ambient_permille,
               uint32_t background_rgba, uint32_t* out_rgba, void* stream);
@@ -359,7 +363,8 @@ typedef struct {
    tiled -- 8x8 pixel tiles, tile rows top to bottom, tiles left to right,
    pixels row-major inside a tile, partial edge tiles holding only in-image
    pixels; otherwise row-major pixels.  The samples of one pixel are
-   consecutive. */
+   consecutive.  SVO_ERANGE for a side above 2^20 pixels or more than
+   0xff000000 rays. */
 int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream);
 
 /* Ambient-occlusion rays from primary hits: for each of the n primary rays

@@ -44,6 +44,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr uint32_t kFar = 0xFFFFFFu;
 constexpr uint32_t kXform = 0x80000000u;
 constexpr uint32_t kMaxStreams = 64;
+constexpr uint32_t kMaxImageSide = 1u << 20;   // pixels per image row or column
 
 inline uint32_t nd_mask(uint64_t w) { return (uint32_t)(w & 0xFFu); }
 inline uint32_t nd_c24(uint64_t w) { return (uint32_t)((w >> 8) & 0xFFFFFFu); }
@@ -857,9 +858,11 @@ int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint3
     if ((uint64_t)first_slot + count > S->n_slots) return fail(SVO_EINVAL, "slots [%u, %u) out of range (%u)", first_slot,
                                                                first_slot + count, S->n_slots);
     if (count && !fwd_3x4) return fail(SVO_EINVAL, "fwd_3x4 is NULL");
-    std::vector<Aff> keep(S->fwd.begin() + first_slot, S->fwd.begin() + first_slot + count);
+    // Every map is checked before any is stored: a rejected call leaves all
+    // slots as they were.
+    std::vector<Aff> next(count);
     for (uint32_t j = 0; j < count; ++j) {
-        Aff a;
+        Aff& a = next[j];
         for (int r = 0; r < 3; ++r) {
             for (int c = 0; c < 4; ++c) {
                 const float v = fwd_3x4[12 * j + 4 * r + c];
@@ -869,8 +872,9 @@ int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint3
         }
         Aff inv;
         if (!aff_inverse(a, inv)) return fail(SVO_EINVAL, "transform of slot %u is singular", first_slot + j);
-        S->fwd[first_slot + j] = a;
     }
+    std::vector<Aff> keep(S->fwd.begin() + first_slot, S->fwd.begin() + first_slot + count);
+    std::copy(next.begin(), next.end(), S->fwd.begin() + first_slot);
     HIP_TRY(hipSetDevice(ctx->device));
     const int rc = upload_frames(*S, (hipStream_t)stream);
     if (rc) {
@@ -909,7 +913,11 @@ int queue_slot(svo_ctx* ctx, hipStream_t st, uint32_t& qslot) {
     if (it == ctx->stream_slot.end()) {
         if (ctx->stream_slot.size() >= kMaxStreams) return fail(SVO_ERANGE, "more than %u streams", kMaxStreams);
         qslot = (uint32_t)ctx->stream_slot.size();
-        ctx->stream_slot[st] = qslot;
+        try {
+            ctx->stream_slot[st] = qslot;
+        } catch (const std::bad_alloc&) {
+            return fail(SVO_ENOMEM, "out of host memory");
+        }
     } else {
         qslot = it->second;
     }
@@ -1241,8 +1249,10 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         a.bvh = reinterpret_cast<const svo::BvhNode*>(B.dev + bb);
         HIP_TRY(hipMemcpyAsync(B.dev, B.host, bytes, hipMemcpyHostToDevice, st));
         rc = launch(ctx, cfg, a, st);
+        // recorded even when the launch failed: the copy still reads B.host
+        const hipError_t e = hipEventRecord(B.ev, st);
         if (rc) return rc;
-        HIP_TRY(hipEventRecord(B.ev, st));
+        if (e != hipSuccess) return fail(SVO_EDEVICE, "batch event record failed: %s", hipGetErrorString(e));
         return SVO_OK;
     } catch (const std::bad_alloc&) {
         return fail(SVO_ENOMEM, "out of host memory");
@@ -1416,6 +1426,7 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     Scene* S = find_scene(ctx, scene);
     if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
     if (n == 0 || !sample_rays) return fail(SVO_EINVAL, "svo_tune needs sample rays");
+    if (n > 0xFF000000ull) return fail(SVO_ERANGE, "at most 0xff000000 sample rays");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
     uint32_t* d_id = nullptr;
@@ -1527,6 +1538,9 @@ int svo_shade(svo_ctx* ctx, svo_scene scene, const uint32_t* prim_id, const uint
     if (!prim_id || !out_rgba || (k && !ao_id)) return fail(SVO_EINVAL, "prim_id, out_rgba (and ao_id when k > 0) are required");
     if (samples == 0 || samples > 1024 || k > 64) return fail(SVO_ERANGE, "samples must be 1..1024 and k at most 64");
     if (ambient_permille > 1000) return fail(SVO_EINVAL, "ambient_permille must be at most 1000");
+    // the kernels index pixels in 32 bits: every 8-row band must stay below 2^32
+    if (width > kMaxImageSide || height > kMaxImageSide || (uint64_t)width * height * samples > 0xFF000000ull)
+        return fail(SVO_ERANGE, "image too large (sides at most %u, at most 0xff000000 samples)", kMaxImageSide);
     if ((uint64_t)width * height * samples * (k ? k : 1) >= (1ull << 40)) return fail(SVO_ERANGE, "image too large");
     HIP_TRY(hipSetDevice(ctx->device));
     svo::ShadeArgs a{};
@@ -1551,6 +1565,8 @@ int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_ra
     if (!ctx || !cam || !out_rays) return fail(SVO_EINVAL, "ctx, cam and out_rays are required");
     if (((uintptr_t)out_rays) & 15u) return fail(SVO_EINVAL, "out_rays must be 16-byte aligned");
     if (cam->width == 0 || cam->height == 0 || cam->samples == 0) return fail(SVO_EINVAL, "empty image");
+    if (cam->width > kMaxImageSide || cam->height > kMaxImageSide)
+        return fail(SVO_ERANGE, "image sides must be at most %u", kMaxImageSide);
     if ((uint64_t)cam->width * cam->height * cam->samples > 0xFF000000ull) return fail(SVO_ERANGE, "too many rays");
     if (!(cam->tan_half_fov > 0.f) || !std::isfinite(cam->tan_half_fov)) return fail(SVO_EINVAL, "bad field of view");
     svo::CameraArgs c{};

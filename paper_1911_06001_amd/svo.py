@@ -163,6 +163,31 @@ def validate(nodes, root, max_depth, slot_child) -> PoolInfo:
     return info
 
 
+def _dptr(t, n_elems: int, name: str, itemsize: int = 4):
+    """Device pointer of tensor t after checking that it can hold n_elems
+    contiguous elements of itemsize bytes.  The library takes plain pointers
+    and cannot see buffer sizes, so a short or strided tensor would be read
+    or written out of bounds on the device.  None passes through."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.element_size() != itemsize:
+        raise ValueError("%s must have %d-byte elements (has %d)" % (name, itemsize, t.element_size()))
+    if t.numel() < n_elems:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), n_elems))
+    return t.data_ptr()
+
+
+def _rays_ptr(r, name: str = "rays"):
+    """(pointer, n) of a device ray tensor [n, 8] float32."""
+    if r.dim() != 2 or r.shape[1] != 8:
+        raise ValueError("%s must have shape [n, 8]" % name)
+    return _dptr(r, 8 * r.shape[0], name), int(r.shape[0])
+
+
 def _stream_handle(stream) -> Optional[int]:
     if stream is None:
         import torch
@@ -188,11 +213,10 @@ def _job_array(jobs):
         if fwd is not None:
             fwd = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
             keep.append(fwd)
-        r = j["rays"]
-        arr[i] = Job(int(j["scene"]), _np_ptr(fwd) if fwd is not None else None, r.data_ptr(), r.shape[0],
-                     j["out_id"].data_ptr(), j["out_inst"].data_ptr() if j.get("out_inst") is not None else None,
-                     j["out_t"].data_ptr(),
-                     j["out_normal"].data_ptr() if j.get("out_normal") is not None else None)
+        rp, n = _rays_ptr(j["rays"], "job %d rays" % i)
+        arr[i] = Job(int(j["scene"]), _np_ptr(fwd) if fwd is not None else None, rp, n,
+                     _dptr(j["out_id"], n, "job %d out_id" % i), _dptr(j.get("out_inst"), n, "job %d out_inst" % i),
+                     _dptr(j["out_t"], n, "job %d out_t" % i), _dptr(j.get("out_normal"), 3 * n, "job %d out_normal" % i))
     return arr, keep
 
 
@@ -304,16 +328,16 @@ class Context:
 
     def trace_into(self, scene: int, rays, out_id, out_t, out_inst=None, out_normal=None, stream=None):
         """Trace device rays [n, 8] float32 into preallocated device outputs."""
-        n = rays.shape[0]
-        _check(lib().svo_trace_rays(self._ptr, int(scene), rays.data_ptr(), n, out_id.data_ptr(),
-                                    None if out_inst is None else out_inst.data_ptr(), out_t.data_ptr(),
-                                    None if out_normal is None else out_normal.data_ptr(), _stream_handle(stream)))
+        rp, n = _rays_ptr(rays)
+        _check(lib().svo_trace_rays(self._ptr, int(scene), rp, n, _dptr(out_id, n, "out_id"),
+                                    _dptr(out_inst, n, "out_inst"), _dptr(out_t, n, "out_t"),
+                                    _dptr(out_normal, 3 * n, "out_normal"), _stream_handle(stream)))
 
     def tune(self, scene: int, sample_rays, stream=None) -> Config:
         """Autotune the kernel configuration for `scene` on device sample rays."""
         c = Config()
-        _check(lib().svo_tune(self._ptr, int(scene), sample_rays.data_ptr(), sample_rays.shape[0],
-                              _stream_handle(stream), ctypes.byref(c)))
+        rp, n = _rays_ptr(sample_rays, "sample_rays")
+        _check(lib().svo_tune(self._ptr, int(scene), rp, n, _stream_handle(stream), ctypes.byref(c)))
         return c
 
     def primary_rays(self, cam: Camera, out=None, stream=None):
@@ -322,32 +346,33 @@ class Context:
         n = cam.width * cam.height * cam.samples
         if out is None:
             out = torch.empty((n, 8), dtype=torch.float32, device="cuda:%d" % self.device)
-        if out.shape[0] < n:
-            raise ValueError("output buffer too small")
-        _check(lib().svo_generate_primary_rays(self._ptr, ctypes.byref(cam), out.data_ptr(), _stream_handle(stream)))
+        _check(lib().svo_generate_primary_rays(self._ptr, ctypes.byref(cam), _dptr(out, 8 * n, "out"),
+                                               _stream_handle(stream)))
         return out
 
     def ao_rays(self, rays, hits: "Hits", k: int, seed: int, radius: float, offset: float = 1e-3, out=None,
                 stream=None):
         """k cosine-weighted AO rays per primary ray, as a device tensor [n * k, 8]."""
         import torch
-        n = rays.shape[0]
+        rp, n = _rays_ptr(rays)
         if out is None:
             out = torch.empty((n * k, 8), dtype=torch.float32, device=rays.device)
-        _check(lib().svo_generate_ao_rays(self._ptr, rays.data_ptr(), hits.t.data_ptr(), hits.normal.data_ptr(), n, int(k),
-                                          int(seed) & 0xFFFFFFFF, float(radius), float(offset), out.data_ptr(),
-                                          _stream_handle(stream)))
+        if hits.normal is None:
+            raise ValueError("AO rays need the primary hits' normals")
+        _check(lib().svo_generate_ao_rays(self._ptr, rp, _dptr(hits.t, n, "hits.t"), _dptr(hits.normal, 3 * n, "hits.normal"),
+                                          n, int(k), int(seed) & 0xFFFFFFFF, float(radius), float(offset),
+                                          _dptr(out, 8 * n * int(k), "out"), _stream_handle(stream)))
         return out
 
     def trace_reuse(self, scene: int, rays, hits: "Hits", retraced=None, stream=None):
         """Update `hits` (the previous trace of these rays on this scene) for
         the scene's current transforms, retracing only rays that can change.
         retraced: optional int64 device tensor [1] the retraced count is added to."""
-        _check(lib().svo_trace_rays_reuse(self._ptr, int(scene), rays.data_ptr(), rays.shape[0], hits.id.data_ptr(),
-                                          hits.inst.data_ptr(), hits.t.data_ptr(),
-                                          hits.normal.data_ptr() if hits.normal is not None else None,
-                                          retraced.data_ptr() if retraced is not None else None,
-                                          _stream_handle(stream)))
+        rp, n = _rays_ptr(rays)
+        _check(lib().svo_trace_rays_reuse(self._ptr, int(scene), rp, n, _dptr(hits.id, n, "hits.id"),
+                                          _dptr(hits.inst, n, "hits.inst"), _dptr(hits.t, n, "hits.t"),
+                                          _dptr(hits.normal, 3 * n, "hits.normal"),
+                                          _dptr(retraced, 1, "retraced", itemsize=8), _stream_handle(stream)))
         return hits
 
     def shade(self, scene: int, prim_id, width: int, height: int, samples: int = 1, tiled: bool = True, ao_id=None,
@@ -356,9 +381,12 @@ class Context:
         import torch
         if out is None:
             out = torch.empty((height, width), dtype=torch.int32, device=prim_id.device)
-        _check(lib().svo_shade(self._ptr, int(scene), prim_id.data_ptr(), ao_id.data_ptr() if ao_id is not None else None,
+        n = int(width) * int(height) * int(samples)
+        _check(lib().svo_shade(self._ptr, int(scene), _dptr(prim_id, n, "prim_id"),
+                               _dptr(ao_id, n * int(k), "ao_id") if k else None,
                                int(width), int(height), int(samples), int(bool(tiled)), int(k), int(ambient_permille),
-                               int(background) & 0xFFFFFFFF, out.data_ptr(), _stream_handle(stream)))
+                               int(background) & 0xFFFFFFFF, _dptr(out, int(width) * int(height), "out"),
+                               _stream_handle(stream)))
         return out
 
     def trace_batch(self, jobs, stream=None):

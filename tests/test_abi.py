@@ -109,3 +109,47 @@ def test_validate_instancing_shares_slot_children():
     pool = [_n(0b11, 1), _n(1, 0, 0x80000000 | 0), _n(1, 0, 0x80000000 | 1), LEAF]
     info = svo.validate(np.asarray(pool, np.uint64), 0, 8, np.asarray([3, 3], np.uint32))
     assert info.n_frames == 3 and info.n_shared == 1
+
+
+def test_binding_refuses_host_and_short_buffers():
+    """The binding checks every tensor before its pointer crosses the ABI
+    (which cannot see sizes): host tensors, wrong shapes, element sizes and
+    short or strided buffers raise ValueError without a library call."""
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError, match="device"):
+        svo._dptr(torch.zeros(8), 8, "x")
+    with pytest.raises(ValueError, match="shape"):
+        svo._rays_ptr(torch.zeros(16), "rays")
+    with pytest.raises(ValueError, match="shape"):
+        svo._rays_ptr(torch.zeros(4, 7), "rays")
+    assert svo._dptr(None, 5, "x") is None
+
+
+class _FakeDev:
+    """Stands in for a device tensor: only what the checks read."""
+
+    def __init__(self, numel, itemsize=4, contiguous=True):
+        self.is_cuda = True
+        self._n, self._s, self._c = numel, itemsize, contiguous
+
+    def is_contiguous(self):
+        return self._c
+
+    def element_size(self):
+        return self._s
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_binding_checks_sizes_of_device_buffers():
+    assert svo._dptr(_FakeDev(10), 10, "x") == 4096
+    with pytest.raises(ValueError, match="needs 11"):
+        svo._dptr(_FakeDev(10), 11, "x")
+    with pytest.raises(ValueError, match="contiguous"):
+        svo._dptr(_FakeDev(10, contiguous=False), 1, "x")
+    with pytest.raises(ValueError, match="8-byte"):
+        svo._dptr(_FakeDev(10, itemsize=4), 1, "retraced", itemsize=8)

@@ -260,6 +260,32 @@ def test_transform_updates_are_stream_ordered(ctx, torch_dev):
         parity.assert_parity(parity.compare(parity.to_numpy(hh), ref, ref.margin, rays))
 
 
+def test_rejected_transforms_change_nothing(ctx, torch_dev):
+    """A call rejected for one slot's map (singular) stores none of its maps:
+    a later call that uploads the table again still traces the old ones."""
+    from paper_1911_06001_amd import svo
+    sc = S.tiny_scene(7, K=5, n_slots=2, nested=False)
+    fwd0 = sc.xform(0)
+    bad = fwd0.copy()
+    bad[0, 3] += np.float32(0.25 * sc.root_size)    # a valid, different map for slot 0 ...
+    bad[1, [0, 1, 2, 4, 5, 6, 8, 9, 10]] = 0.0      # ... and a singular one for slot 1
+    rays = S.random_rays(7, 3000, 0.0, sc.root_size)
+    ref = oracle.trace_scene(sc, rays, fwd=fwd0, margin=True)
+    moved = fwd0.copy()
+    moved[0] = bad[0]
+    assert np.count_nonzero(oracle.trace_scene(sc, rays, fwd=moved).id != ref.id) > 0
+    h = ctx.upload_scene(sc)
+    try:
+        ctx.set_transforms(h, fwd0)
+        with pytest.raises(svo.SvoError):
+            ctx.set_transforms(h, bad)
+        ctx.set_transforms(h, fwd0[1:], first=1)   # packs and uploads every slot's map
+        g = _trace(ctx, torch_dev, h, rays)
+    finally:
+        ctx.free_scene(h)
+    parity.assert_parity(parity.compare(g, ref, ref.margin, rays))
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
 def test_inline_contained_frames(ctx, torch_dev, seed):
     """Shrunk, rotated subtrees stay inside their static cells: the walk

@@ -71,3 +71,23 @@ def test_primary_image_from_oracle_hits(env):
     # a pixel can differ only where its ray's id differs, and those rays graze
     assert diff.reshape(-1)[pix[mism]].sum() == diff.sum()
     assert np.all(ref_hits.margin[mism] < 1e-6)
+
+
+def test_oversized_images_are_refused_before_launch(env):
+    """A side above 2^20 pixels is refused on the host for shading and for
+    primary rays (the kernels index the pixels of an 8-row band in 32 bits),
+    so no kernel runs with such a shape; the buffers here are tiny on
+    purpose and never touched."""
+    torch, svo, ctx, sc, h = env
+    ids = torch.zeros(64, dtype=torch.int32, device="cuda")
+    img = torch.zeros(64, dtype=torch.int32, device="cuda")
+    for W, H in ((1 << 29, 1), (1, 1 << 29), ((1 << 20) + 1, 1)):
+        rc = svo.lib().svo_shade(ctx._ptr, h, ids.data_ptr(), None, W, H, 1, 1, 0, 200, 0, img.data_ptr(), None)
+        assert rc == svo.SVO_ERANGE, (W, H, rc)
+        cam = svo.make_camera((0, 0, -5), (0, 0, 0), (0, 1, 0), 45.0, W, H)
+        rc = svo.lib().svo_generate_primary_rays(ctx._ptr, cam, img.data_ptr(), None)
+        assert rc == svo.SVO_ERANGE, (W, H, rc)
+    torch.cuda.synchronize()
+    assert int(img.abs().sum()) == 0
+    with pytest.raises(ValueError):
+        ctx.shade(h, ids, 16, 16)            # 256 ids needed, 64 given: caught in the binding
