@@ -29,6 +29,26 @@ KERNEL_SOURCES = ["paper_1911_06001_amd/csrc/svo_trace.hip", "paper_1911_06001_a
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "trace_kernel_terrain1024_1080p_pmc.txt")
 
 
+# The paper's own measurements (Sec. 5.1, Fig. 7: average render time per
+# 1280x768 frame of a depth-11 car model, static camera), on NVIDIA GPUs.
+# Context only, not a target: another model, resolution and machine, and the
+# frame time may include display.  Mrays/s is derived here as 1280 * 768
+# rays per frame (one ray per pixel) / render time.
+def _paper_rate(ms):
+    return round(1280 * 768 / (ms * 1e-3) / 1e6, 2)
+
+
+PAPER_CONTEXT = {
+    "source": "Sec. 5.1, Fig. 7 (render time per 1280x768 frame, depth-11 car, 1 ray/pixel derived)",
+    "unit": "Mrays/s",
+    "gpus": {
+        gpu: {"static": _paper_rate(st), "animated": _paper_rate(an), "animated_opt": _paper_rate(op)}
+        for gpu, st, an, op in (("Quadro T1000", 61.68, 80.78, 62.05), ("GeForce GTX 680", 42.86, 56.16, 40.18),
+                                ("Quadro P5000", 16.74, 21.12, 14.77))
+    },
+}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -531,6 +551,7 @@ def main():
         "roofline": roof,
         "ceilings": ceilings,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "serving": serving,
         "instances": instances,
         "terrain4096": c5,
