@@ -358,8 +358,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how rays "
-              "would shard); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (rays would shard across GPUs "
+              "with the pool replicated on each); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

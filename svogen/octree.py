@@ -27,7 +27,7 @@ from typing import Callable, Dict, Optional, Tuple
 
 import numpy as np
 
-EMPTY, FULL, PARTIAL, GRAFT = 0, 1, 2, 3
+EMPTY, FULL, PARTIAL, SLOT = 0, 1, 2, 3
 FAR = 0xFFFFFF
 XFORM_BIT = 0x80000000
 NONE = 0xFFFFFFFF
@@ -42,8 +42,8 @@ class Tree:
     nodes: np.ndarray            # uint64 [n]
     level: np.ndarray            # int32 [n]
     coord: np.ndarray            # int64 [n, 3]
-    kind: np.ndarray             # uint8 [n]  FULL / PARTIAL / GRAFT
-    child_start: np.ndarray      # int64 [n]  (-1 for leaves / grafts)
+    kind: np.ndarray             # uint8 [n]  FULL / PARTIAL / SLOT
+    child_start: np.ndarray      # int64 [n]  (-1 for leaves / slot cells)
     K: int                       # leaf level (height)
 
     @property
@@ -67,30 +67,30 @@ def _encode_interior(idx, mask, start):
 
 
 def build_tree(K: int, classify: Callable, colour: Optional[Callable] = None,
-               grafts: Optional[Dict[Tuple[int, int, int, int], Tuple[int, int]]] = None) -> Tree:
+               slot_nodes: Optional[Dict[Tuple[int, int, int, int], Tuple[int, int]]] = None) -> Tree:
     """Build a breadth-first pool.
 
-    grafts: {(level, x, y, z): (slot, mask)} -- cells emitted as transformed
+    slot_nodes: {(level, x, y, z): (slot, mask)} -- cells emitted as transformed
     nodes with the given child mask (their content lives in another tree).
     """
-    grafts = grafts or {}
-    graft_levels: Dict[int, Dict[Tuple[int, int, int], Tuple[int, int]]] = {}
-    for (l, x, y, z), v in grafts.items():
+    slot_nodes = slot_nodes or {}
+    slot_levels: Dict[int, Dict[Tuple[int, int, int], Tuple[int, int]]] = {}
+    for (l, x, y, z), v in slot_nodes.items():
         if l <= 0 or l > K:
-            raise ValueError("graft level must be in 1..K")
-        graft_levels.setdefault(l, {})[(x, y, z)] = v
+            raise ValueError("slot level must be in 1..K")
+        slot_levels.setdefault(l, {})[(x, y, z)] = v
 
-    def classify_with_grafts(l, coords):
+    def classify_with_slots(l, coords):
         k = np.asarray(classify(l, coords), dtype=np.uint8).copy()
-        g = graft_levels.get(l)
+        g = slot_levels.get(l)
         if g:
             for j, c in enumerate(map(tuple, coords.tolist())):
                 if c in g:
-                    k[j] = GRAFT
+                    k[j] = SLOT
         return k
 
     root = np.zeros((1, 3), dtype=np.int64)
-    rk = classify_with_grafts(0, root)
+    rk = classify_with_slots(0, root)
     empty = Tree(np.zeros(0, np.uint64), np.zeros(0, np.int32), np.zeros((0, 3), np.int64),
                  np.zeros(0, np.uint8), np.zeros(0, np.int64), K)
     if rk[0] == EMPTY:
@@ -111,7 +111,7 @@ def build_tree(K: int, classify: Callable, colour: Optional[Callable] = None,
             lv_counts.append(np.zeros(0, np.int64))
             break
         ch = (parents[:, None, :] * 2 + OCT[None, :, :]).reshape(-1, 3)
-        ck = classify_with_grafts(l + 1, ch)
+        ck = classify_with_slots(l + 1, ch)
         exist = (ck != EMPTY).reshape(-1, 8)
         mask = (exist * (1 << np.arange(8))[None, :]).sum(1)
         if np.any(mask == 0):
@@ -150,13 +150,13 @@ def build_tree(K: int, classify: Callable, colour: Optional[Callable] = None,
             if colour is not None:
                 col = np.asarray(colour(l, lv_coords[l][full]), dtype=np.uint64) & np.uint64(0xFFFFFFFF)
             nodes[idx[full]] = col << np.uint64(32)
-        gr = kk == GRAFT
+        gr = kk == SLOT
         if gr.any():
-            g = graft_levels[l]
+            g = slot_levels[l]
             for j in np.nonzero(gr)[0]:
                 slot, gmask = g[tuple(lv_coords[l][j].tolist())]
                 if gmask == 0 or gmask > 0xFF:
-                    raise ValueError("graft mask must be 1..255")
+                    raise ValueError("slot mask must be 1..255")
                 nodes[a + j] = np.uint64(gmask) | (np.uint64(XFORM_BIT | slot) << np.uint64(32))
     return Tree(nodes, level, coord, kind, child_start, K)
 

@@ -399,10 +399,9 @@ def instanced_scene(seed: int = 3, n_inst: int = 64, world_K: int = 12) -> Scene
             cells.append((L, xyz))
     if len(cells) < n_inst:
         raise RuntimeError("could not place all instances")
-    grafts = {}
+    slot_nodes = {}
     for s, (L, xyz) in enumerate(cells):
-        grafts[(L,) + xyz] = (s, inst[s % 4].root_mask)
-    graft_set = {(L,) + xyz for (L, xyz) in cells}
+        slot_nodes[(L,) + xyz] = (s, inst[s % 4].root_mask)
 
     def classify(l, c):
         out = np.zeros(c.shape[0], np.uint8)
@@ -414,7 +413,7 @@ def instanced_scene(seed: int = 3, n_inst: int = 64, world_K: int = 12) -> Scene
                     break
         return out
 
-    world = ot.build_tree(world_K, classify, None, grafts=grafts)
+    world = ot.build_tree(world_K, classify, None, slot_nodes=slot_nodes)
     nodes, bases = ot.concat([world] + inst)
     slot_child = np.array([bases[1 + s % 4] + int(inst[s % 4].child_start[0]) for s in range(n_inst)], np.uint32)
     slot_cell = np.array([[0.0, 0.0, 0.0, float(1 << inst[s % 4].K)] for s in range(n_inst)], np.float32)
