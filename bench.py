@@ -313,6 +313,7 @@ def serve_latency(ctx, terrain, terrain_handle, n_requests, loads, warm=100):
     ctx.free_scene(hs)
     return {"requests": n_requests, "warmup_requests": warm, "saturation_rps": round(rate, 1),
             "hbm_budget_bytes": budget, "policy": srv.policy, "max_rays_per_step": srv.max_rays,
+            "solo_rays_per_step": srv.solo_rays, "step_streams": srv.inflight_steps,
             "mix": "sphere64 + terrain1024 scenes, 256^2/720p/1080p/2048x1152, 1-5 rays per pixel, Poisson arrivals",
             "points": points}
 

@@ -7,13 +7,16 @@ resident; a request only brings its ray and output buffers.
 
   batched  requests are admitted while their footprint fits the budget;
            every step packs up to `max_rays_per_step` rays from the admitted
-           requests (large requests are split across steps) into one
+           requests (large requests are split across steps, unless one is
+           the only request with work: then up to `solo_rays_per_step`) into one
            persistent launch, each job with its own scene and animation
-           frame; two steps are kept in flight so the host prepares step k+1
-           while the device runs step k.  With graph=True each in-flight slot
-           owns a launch plan (svo_plan_*) whose launch was captured once into
-           a HIP graph; a step writes its jobs into the plan's staging and
-           replays the graph.  Otherwise a step is one svo_trace_batch call.
+           frame; two steps are kept in flight, on two streams, so the host
+           prepares step k+1 while the device runs step k, and step k+1's
+           launch takes the CUs that step k frees while its last rays drain.
+           With graph=True each in-flight slot owns a launch plan (svo_plan_*)
+           whose launch was captured once into a HIP graph; a step writes its
+           jobs into the plan's staging and replays the graph.  Otherwise a
+           step is one svo_trace_batch call.
   single   the baseline: one request per svo_trace_rays launch, first come,
            first served, the next one starting when the previous finished.
 
@@ -95,6 +98,9 @@ class _Active:
     n: int = -1              # rays of the current phase (primary, then AO)
     phase: int = 0           # 0: primary rays; 1: AO rays from the primary hits
     primary_out: Optional[dict] = None
+    ready: "object" = None   # device event after which the current phase's rays exist
+    step_events: list = field(default_factory=list)   # events of the steps holding this phase's chunks
+    done_at: float = 0.0     # latest completion of its retired steps (steps on two streams may end out of order)
 
     def __post_init__(self):
         if self.n < 0:
@@ -119,10 +125,14 @@ class Scheduler:
             ref_rate: a small request overtakes large ones that arrived a
             little earlier, but no request is passed by work that arrived
             after its deadline, which bounds the stretch of large requests.
+    A request that is the only one with work left may take up to
+    `solo_rays` rays in one step (0: no exception): there is nothing to
+    interleave with it, and every extra step costs a launch and its drain.
     """
 
     def __init__(self, budget: int, max_rays: int, policy: str = "edf", min_chunk: int = 1 << 16,
-                 max_jobs: int = 256, max_frames: int = 2047, slack: float = 3.0, ref_rate: float = 4e9):
+                 max_jobs: int = 256, max_frames: int = 2047, slack: float = 3.0, ref_rate: float = 4e9,
+                 solo_rays: int = 0):
         if policy not in ("fifo", "fair", "edf"):
             raise ValueError(policy)
         self.slack = float(slack)
@@ -133,6 +143,7 @@ class Scheduler:
         self.min_chunk = int(min_chunk)
         self.max_jobs = int(max_jobs)
         self.max_frames = int(max_frames)
+        self.solo_rays = int(solo_rays)
         self.used = 0
         self.max_used = 0
 
@@ -164,7 +175,12 @@ class Scheduler:
         work = [a for a in active if a.n > a.next_ray]
         if self.policy == "edf":
             work.sort(key=lambda a: a.req.arrival + self.slack * a.req.total_rays / self.ref_rate)
-        chunks, left, frames = [], self.max_rays, 0
+        left = self.max_rays
+        if len(work) == 1:
+            # splitting lets other requests interleave; with none to interleave
+            # it only adds a launch (and its drain) per extra step
+            left = max(left, self.solo_rays)
+        chunks, frames = [], 0
         share = left
         if self.policy == "fair" and work:
             share = max(self.min_chunk, left // min(len(work), self.max_jobs))
@@ -205,7 +221,8 @@ def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: 
 
 class Server:
     def __init__(self, ctx: svo.Context, scenes: Dict[str, SceneEntry], hbm_budget: int,
-                 max_rays_per_step: int = 1 << 22, inflight_steps: int = 2, keep_outputs: bool = False,
+                 max_rays_per_step: int = 1 << 22, solo_rays_per_step: int = 1 << 24, inflight_steps: int = 2,
+                 keep_outputs: bool = False,
                  policy: str = "edf", graph: bool = False, max_jobs: int = 16, max_frames: int = 64):
         import torch
         self.torch = torch
@@ -213,11 +230,16 @@ class Server:
         self.scenes = scenes
         self.budget = int(hbm_budget)
         self.max_rays = int(max_rays_per_step)
+        self.solo_rays = int(solo_rays_per_step)
         self.inflight_steps = int(inflight_steps)
         self.keep = keep_outputs
         self.policy = policy
         self.stream = torch.cuda.current_stream()
         self.dev = torch.device("cuda:%d" % ctx.device)
+        # one stream per in-flight step (default priority): the next step's
+        # launch takes the CUs that the previous launch frees while it drains,
+        # instead of waiting behind its slowest rays
+        self.step_streams = [torch.cuda.Stream(device=self.dev) for _ in range(self.inflight_steps)]
         self.frames = {k: 1 + ctx.scene_stats(e.handle).n_slots for k, e in scenes.items()}
         self.max_jobs = int(max_jobs)
         # room for at least two jobs of the largest scene per step
@@ -265,12 +287,19 @@ class Server:
                     out_t=t.empty(n, dtype=t.float32, device=self.dev),
                     out_normal=t.empty((n, 3), dtype=t.float32, device=self.dev))
 
-    def _start_ao(self, a: "_Active"):
+    def _start_ao(self, a: "_Active", stream):
         """Second phase of a request: AO rays from its primary hits, generated
-        on the device (stream-ordered after the primary trace)."""
+        on the device.  Called once the request's last primary chunk has been
+        enqueued: the generation waits on `stream` for every step that holds
+        a primary chunk, and the steps of the AO phase wait for it."""
         from .svo import Hits
+        for e in a.step_events:
+            stream.wait_event(e)
         hits = Hits(a.out["out_id"], a.out["out_inst"], a.out["out_t"], a.out["out_normal"])
-        ao = self.ctx.ao_rays(a.rays, hits, k=a.req.ao, seed=a.req.seed, radius=a.req.ao_radius, stream=self.stream)
+        ao = self.ctx.ao_rays(a.rays, hits, k=a.req.ao, seed=a.req.seed, radius=a.req.ao_radius, stream=stream)
+        a.ready = self.torch.cuda.Event()
+        a.ready.record(stream)
+        a.step_events = []
         a.primary_out, a.primary_rays = a.out, a.rays
         a.rays, a.out = ao, self._buffers(ao.shape[0])
         a.phase, a.n, a.next_ray = 1, ao.shape[0], 0
@@ -290,7 +319,8 @@ class Server:
         active: List[_Active] = []
         inflight = collections.deque()   # (event, [(active, n_rays)])
         results: List[Result] = []
-        sched = Scheduler(self.budget, self.max_rays, self.policy, max_jobs=self.max_jobs, max_frames=self.max_frames)
+        sched = Scheduler(self.budget, self.max_rays, self.policy, max_jobs=self.max_jobs, max_frames=self.max_frames,
+                          solo_rays=self.solo_rays)
         step = 0
         self.scheduler = sched
         t.cuda.synchronize()
@@ -304,6 +334,8 @@ class Server:
             res = Result(req, admitted=time.perf_counter() - t0)
             a = _Active(req, res, rays, self._buffers(req.rays), np.ascontiguousarray(entry.xform(req.frame), np.float32),
                         frames=self.frames[req.scene])
+            a.ready = t.cuda.Event()
+            a.ready.record(self.stream)
             active.append(a)
             return a
 
@@ -311,17 +343,15 @@ class Server:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # retire finished steps (in stream order)
+            # retire finished steps (in submission order)
             while inflight and inflight[0][0].query():
                 ev, chunks = inflight.popleft()
                 done_at = start_ev.elapsed_time(ev) * 1e-3
                 for a, _, _ in chunks:
                     a.pending_chunks -= 1
-                    if a.pending_chunks == 0 and a.next_ray >= a.n:
-                        if a.phase == 0 and a.req.ao:
-                            self._start_ao(a)
-                            continue
-                        a.res.completed = done_at
+                    a.done_at = max(a.done_at, done_at)
+                    if a.pending_chunks == 0 and a.next_ray >= a.n and (a.phase == 1 or not a.req.ao):
+                        a.res.completed = a.done_at
                         if self.keep:
                             a.res.out = a.primary_out or a.out
                             a.res.out["rays"] = a.primary_rays if a.phase else a.rays
@@ -339,19 +369,31 @@ class Server:
                                  out_id=a.out["out_id"][lo:hi], out_inst=a.out["out_inst"][lo:hi],
                                  out_t=a.out["out_t"][lo:hi], out_normal=a.out["out_normal"][lo:hi])
                             for a, lo, hi in chunks]
+                    k = step % self.inflight_steps
+                    st = self.step_streams[k]
+                    for a in {id(a): a for a, _, _ in chunks}.values():
+                        st.wait_event(a.ready)     # its rays exist (generated on another stream)
                     if self.graph:
-                        # this slot's previous replay has retired (at most
-                        # inflight_steps - 1 steps are still in flight)
-                        k = step % self.inflight_steps
+                        # this slot's previous replay has retired (steps
+                        # retire in order and at most inflight_steps - 1 are
+                        # still in flight)
                         self._plans[k].set_jobs(jobs)
-                        with t.cuda.stream(self.stream):
+                        with t.cuda.stream(st):
                             self._graphs[k].replay()
                     else:
-                        self.ctx.trace_batch(jobs, stream=self.stream)
+                        self.ctx.trace_batch(jobs, stream=st)
                     step += 1
                     ev = t.cuda.Event(enable_timing=True)
-                    ev.record(self.stream)
+                    ev.record(st)
                     inflight.append((ev, chunks))
+                    for a, _, _ in chunks:
+                        a.step_events.append(ev)
+                    # a request whose last primary chunk is in this step gets
+                    # its AO rays generated behind it, so its AO phase can go
+                    # into the next step without waiting for this one to retire
+                    for a in {id(a): a for a, _, _ in chunks}.values():
+                        if a.phase == 0 and a.req.ao and a.next_ray >= a.n:
+                            self._start_ao(a, st)
                     continue
             # nothing to submit: wait for the device or the next arrival
             if inflight:

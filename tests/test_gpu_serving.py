@@ -34,16 +34,18 @@ def setup():
     ctx.close()
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_each_result_same_alone_and_in_the_mix(setup, graph):
+@pytest.mark.parametrize("graph,solo", [(False, 0), (True, 0), (False, 1 << 24)])
+def test_each_result_same_alone_and_in_the_mix(setup, graph, solo):
     """Continuous batching (eager batched launches, or a captured plan
-    launch replayed per step): every request's outputs equal tracing it alone."""
+    launch replayed per step; requests split across steps, or a lone one
+    taken whole): every request's outputs equal tracing it alone."""
     torch, ctx, entries, scenes = setup
     from paper_1911_06001_amd import serve
     reqs = serve.poisson_requests(24, 4000.0, 3, ["sphere", "terrain"],
                                   resolutions=((64, 64), (160, 90), (256, 144), (96, 200)), samples=(1, 3))
     budget = 3 * max(r.footprint for r in reqs)
-    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=60000, keep_outputs=True, graph=graph)
+    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=60000, solo_rays_per_step=solo,
+                       keep_outputs=True, graph=graph)
     try:
         res = srv.run(reqs, mode="batched")
     finally:
@@ -88,7 +90,8 @@ def test_requests_with_ao_phase(setup, graph):
     shapes = {"sphere": (48, 40, 2, 3), "terrain": (120, 72, 1, 2)}
     reqs = serve.poisson_requests(12, 3000.0, 8, ["sphere", "terrain"], shapes=shapes)
     budget = 3 * max(r.footprint for r in reqs)
-    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=20000, keep_outputs=True, graph=graph)
+    srv = serve.Server(ctx, entries, hbm_budget=budget, max_rays_per_step=20000, solo_rays_per_step=0,
+                       keep_outputs=True, graph=graph)
     try:
         res = srv.run(reqs, mode="batched")
     finally:

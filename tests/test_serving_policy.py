@@ -115,3 +115,27 @@ def test_request_that_cannot_fit_a_step_is_rejected():
         s.admit(collections.deque([big]), lambda r: r, frames_of=lambda r: 257)
     ok = Request(1, 0.0, "small", 0, 64, 64, 1)
     assert len(s.admit(collections.deque([ok]), lambda r: r, frames_of=lambda r: 9)) == 1
+
+
+@pytest.mark.parametrize("policy", ["fifo", "fair", "edf"])
+def test_a_lone_request_takes_up_to_the_solo_cap(policy):
+    """With solo_rays, a request that is the only one with work left goes in
+    one step (up to that cap); beside another request the step cap holds."""
+    big = Request(0, 0.0, "a", 0, 2048, 1152, 4)          # 9,437,184 rays
+    small = Request(1, 0.0, "a", 0, 256, 256, 1)
+    s = Scheduler(1 << 40, 1 << 22, policy=policy, solo_rays=1 << 24)
+    a = _Active(big, Result(big), None, {}, None)
+    chunks = s.plan([a])
+    assert chunks == [(a, 0, big.rays)]
+    # capped at solo_rays when the lone request is larger still
+    s2 = Scheduler(1 << 40, 1 << 22, policy=policy, solo_rays=1 << 23)
+    a2 = _Active(big, Result(big), None, {}, None)
+    assert [(lo, hi) for _, lo, hi in s2.plan([a2])] == [(0, 1 << 23)]
+    # two requests with work: the step cap applies
+    a3, b3 = _Active(big, Result(big), None, {}, None), _Active(small, Result(small), None, {}, None)
+    chunks = s.plan([a3, b3])
+    assert sum(hi - lo for _, lo, hi in chunks) <= 1 << 22
+    # solo_rays = 0 (the default) keeps the step cap for a lone request too
+    s4 = Scheduler(1 << 40, 1 << 22, policy=policy)
+    a4 = _Active(big, Result(big), None, {}, None)
+    assert [(lo, hi) for _, lo, hi in s4.plan([a4])] == [(0, 1 << 22)]
