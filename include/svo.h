@@ -175,8 +175,11 @@ int svo_get_scene_stats(svo_ctx* ctx, svo_scene scene, svo_scene_stats* out);
 /* Set the parent-relative forward maps of slots [first_slot, first_slot +
    count).  fwd_3x4: host, count * 12 floats, row-major 3x4 [L | b] with
    x_parent = L x_local + b (paper Eq. 3 inverts this per frame; nested slots
-   compose).  The library composes and inverts in FP64 on the host, packs one
-   64-byte FP32 record per frame and copies the whole table on `stream`;
+   compose).  The library composes and inverts in FP64 on the host and packs
+   one 64-byte FP32 record per frame.  A scene of at most 8 slots carries
+   that table to each trace in the kernel arguments: this call then does no
+   device work, and every trace keeps the transforms current when it was
+   enqueued, on any stream.  A larger scene's table is copied on `stream`;
    traces enqueued on `stream` afterwards see the new transforms, earlier
    ones the old (two device tables alternate, so the second call after a
    trace rewrites the table that trace reads: a trace on another stream must

@@ -298,6 +298,8 @@ struct Scene {
     unsigned char* h_stage[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
     size_t table_bytes = 0;
+    bool inline_tab = false;            // small enough for the table to travel in a launch's arguments
+    bool dev_current = true;            // the current device table holds the current transforms
     int cur = 0;                        // table the next trace reads
     uint32_t n_frames = 1;              // 1 + n_slots records per table
     // classification of the current table
@@ -640,15 +642,23 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
     return SVO_OK;
 }
 
-int upload_frames(Scene& S, hipStream_t stream) {
+// Build the next table in the staging buffer not in use and make it current.
+// With to_device the table is also copied into the device table not in use,
+// on `stream`.  Without (transform updates of a scene whose table fits a
+// launch's arguments) there is no device work: traces then copy the staging
+// table into their arguments when they are enqueued.
+int upload_frames(Scene& S, hipStream_t stream, bool to_device) {
     const int k = S.cur ^ 1;
     // the staging buffer may still feed an earlier copy
     HIP_TRY(hipEventSynchronize(S.ev[k]));
     TableInfo T;
     int rc = build_frames(S, S.fwd, S.h_stage[k], T);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(S.d_table[k], S.h_stage[k], S.table_bytes, hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipEventRecord(S.ev[k], stream));
+    if (to_device) {
+        HIP_TRY(hipMemcpyAsync(S.d_table[k], S.h_stage[k], S.table_bytes, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipEventRecord(S.ev[k], stream));
+    }
+    S.dev_current = to_device;
     S.cur = k;
     S.n_cand = T.n_cand;
     S.stack_levels = T.stack_levels;
@@ -781,6 +791,9 @@ int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t r
         }
         S->n_frames = 1 + n_slots;
         S->table_bytes = table_size(S->n_frames, n_slots);
+        // at most 16 slots: every candidate takes the sorted path, which
+        // needs no hierarchy, so records, candidates and spheres suffice
+        S->inline_tab = n_slots <= svo::kMaxSortedCand && bvh_offset(S->n_frames, n_slots) <= svo::kInlineTableBytes;
         const size_t fb = S->table_bytes;
         for (int k = 0; k < 2; ++k) {
             if (hipMalloc((void**)&S->d_table[k], fb) != hipSuccess ||
@@ -798,7 +811,7 @@ int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t r
             }
         }
         for (int k = 0; k < 2; ++k) (void)hipEventRecord(S->ev[k], 0);
-        rc = upload_frames(*S, 0);
+        rc = upload_frames(*S, 0, true);
         if (rc == SVO_OK && hipStreamSynchronize(0) != hipSuccess) rc = fail(SVO_EDEVICE, "frame upload failed");
         if (rc) {
             free_scene(*S);
@@ -876,7 +889,7 @@ int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint3
     std::vector<Aff> keep(S->fwd.begin() + first_slot, S->fwd.begin() + first_slot + count);
     std::copy(next.begin(), next.end(), S->fwd.begin() + first_slot);
     HIP_TRY(hipSetDevice(ctx->device));
-    const int rc = upload_frames(*S, (hipStream_t)stream);
+    const int rc = upload_frames(*S, (hipStream_t)stream, !S->inline_tab);
     if (rc) {
         std::copy(keep.begin(), keep.end(), S->fwd.begin() + first_slot);
         return rc;
@@ -962,7 +975,8 @@ size_t fit_lds(const svo_ctx* ctx, svo::TraceArgs& a, uint32_t& waves) {
 }
 
 // Size LDS (see fit_lds) and launch.
-int launch(svo_ctx* ctx, const svo_config& cfg, svo::TraceArgs& a, hipStream_t st) {
+int launch(svo_ctx* ctx, const svo_config& cfg, svo::TraceArgs& a, hipStream_t st, const unsigned char* inline_tab = nullptr,
+           size_t inline_bytes = 0) {
     a.tile_stride = tile_stride((a.n_rays + 63) / 64);
     svo_config c = cfg;
     const size_t lds = fit_lds(ctx, a, c.waves_per_block);
@@ -975,7 +989,7 @@ int launch(svo_ctx* ctx, const svo_config& cfg, svo::TraceArgs& a, hipStream_t s
     const uint64_t cap = (uint64_t)ctx->n_cu * resident_blocks(ctx, c, lds);
     L.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
     L.lds_bytes = lds;
-    const hipError_t e = svo::launch_trace(a, L, st);
+    const hipError_t e = svo::launch_trace(a, L, st, inline_tab, inline_bytes);
     if (e != hipSuccess) return fail(SVO_EDEVICE, "trace launch failed: %s", hipGetErrorString(e));
     return SVO_OK;
 }
@@ -1135,6 +1149,16 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     // the hierarchy is walked only past kMaxSortedCand candidates
     a.n_bvh_total = S->n_cand > svo::kMaxSortedCand ? S->n_bvh : 0u;
     a.bvh_depth = S->bvh_depth;
+    // transforms changed since the device table was written: the table
+    // travels in the arguments
+    const unsigned char* tab = nullptr;
+    size_t tab_bytes = 0;
+    if (!S->dev_current) {
+        tab = S->h_stage[S->cur];
+        tab_bytes = bvh_offset(S->n_frames, S->n_slots);
+        a.inline_off_cand = (uint32_t)cand_offset(S->n_frames);
+        a.inline_off_sph = (uint32_t)sphere_offset(S->n_frames, S->n_slots);
+    }
     a.n_jobs = 1;
     a.n_frames = S->n_frames;
     a.n_cand_total = S->n_cand + S->n_inline;
@@ -1149,7 +1173,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     fill_common(cfg, a);
     a.reuse = reuse ? 1u : 0u;
     a.retraced = retraced;
-    return launch(ctx, cfg, a, st);
+    return launch(ctx, cfg, a, st, tab, tab_bytes);
 }
 
 }  // namespace

@@ -101,6 +101,14 @@ struct alignas(16) LaunchHdr {
 };
 static_assert(sizeof(LaunchHdr) == 64, "launch header must be 64 bytes");
 
+// A one-job launch of a small scene whose transforms changed since its last
+// upload carries the frame table (records, candidates, spheres; no
+// hierarchy) in its kernel arguments (TraceArgsInline): no copy and no event
+// per transform update, and the launch keeps the transforms it was enqueued
+// with.  Larger arguments cost every launch a little, so launches that can
+// read an up-to-date device table keep the plain arguments.
+constexpr uint32_t kInlineTableBytes = 768;
+
 // In a plan launch (hdr != nullptr) n_jobs, n_frames, n_cand_total,
 // n_bvh_total and lds_nodes are capacities that size the LDS layout, and the header holds
 // the counts; n_rays, tile_stride and cache_src are ignored.
@@ -131,6 +139,13 @@ struct TraceArgs {
     unsigned long long* retraced;  // reuse: rays traced again are added here (nullable)
     uint64_t tile_stride;     // claim i covers tile (i * tile_stride) mod tiles (coprime: a permutation)
     uint32_t step_limit;
+    // TraceArgsInline launches: frames, cand and spheres are read from the
+    // inline table at these byte offsets instead of the pointers above
+    uint32_t inline_off_cand, inline_off_sph;
+};
+
+struct TraceArgsInline : TraceArgs {
+    alignas(16) unsigned char inline_tab[kInlineTableBytes];
 };
 
 struct LaunchCfg {
@@ -184,6 +199,9 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block);
 // device; done once when a context is created, so that no launch (eager or
 // captured into a graph) changes the kernel's attributes.
 hipError_t prepare_trace(size_t max_lds);
-hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream);
+// inline_tab (nullable): the frame table to pass in the arguments (at most
+// kInlineTableBytes; one-job launches with sorted candidates only).
+hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream,
+                        const unsigned char* inline_tab = nullptr, size_t inline_bytes = 0);
 
 }  // namespace svo

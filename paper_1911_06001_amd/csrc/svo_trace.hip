@@ -34,6 +34,9 @@
 // starts from zero.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <type_traits>
+
 #include "svo_internal.h"
 
 namespace svo {
@@ -206,9 +209,10 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
 // kSingle: a one-job launch (the job in the arguments), whose pool, cache
 // size and table offsets are then launch-wide values (scalar registers)
 // rather than per-lane ones.
-template <bool kSorted, bool kSingle>
+// kInline: the frame table comes in the arguments (TraceArgsInline).
+template <bool kSorted, bool kSingle, bool kInline = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 6 : 1, 8))) void trace_kernel(
-    TraceArgs a) {
+    typename std::conditional<kInline, TraceArgsInline, TraceArgs>::type a) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* p = smem;
     uint64_t* lds_nodes = reinterpret_cast<uint64_t*>(p);
@@ -271,13 +275,23 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         n_jobs = 0;
     }
     for (uint32_t i = threadIdx.x; i < fill_nodes; i += blockDim.x) lds_nodes[i] = cache_src[i];
+    // the frame table: in the arguments (small one-job launches) or in
+    // device memory
+    const FrameRec* src_frames = a.frames;
+    const float4* src_sph = a.spheres;
+    const uint32_t* src_cand = a.cand;
+    if constexpr (kInline) {
+        src_frames = reinterpret_cast<const FrameRec*>(a.inline_tab);
+        src_sph = reinterpret_cast<const float4*>(a.inline_tab + a.inline_off_sph);
+        src_cand = reinterpret_cast<const uint32_t*>(a.inline_tab + a.inline_off_cand);
+    }
     {
-        const uint4* src = reinterpret_cast<const uint4*>(a.frames);
+        const uint4* src = reinterpret_cast<const uint4*>(src_frames);
         uint4* dst = reinterpret_cast<uint4*>(lds_frames);
         for (uint32_t i = threadIdx.x; i < n_frames * 4u; i += blockDim.x) dst[i] = src[i];
     }
-    for (uint32_t i = threadIdx.x; i < n_frames; i += blockDim.x) lds_sph[i] = a.spheres[i];
-    for (uint32_t i = threadIdx.x; i < n_cand_total; i += blockDim.x) lds_cand[i] = a.cand[i];
+    for (uint32_t i = threadIdx.x; i < n_frames; i += blockDim.x) lds_sph[i] = src_sph[i];
+    for (uint32_t i = threadIdx.x; i < n_cand_total; i += blockDim.x) lds_cand[i] = src_cand[i];
     {
         const uint4* src = reinterpret_cast<const uint4*>(a.bvh);
         uint4* dst = reinterpret_cast<uint4*>(lds_bvh);
@@ -852,7 +866,8 @@ hipError_t prepare_trace(size_t max_lds) {
     const void* kernels[] = {reinterpret_cast<const void*>(&trace_kernel<true, true>),
                              reinterpret_cast<const void*>(&trace_kernel<true, false>),
                              reinterpret_cast<const void*>(&trace_kernel<false, true>),
-                             reinterpret_cast<const void*>(&trace_kernel<false, false>)};
+                             reinterpret_cast<const void*>(&trace_kernel<false, false>),
+                             reinterpret_cast<const void*>(&trace_kernel<true, true, true>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
         if (e != hipSuccess) return e;
@@ -860,8 +875,17 @@ hipError_t prepare_trace(size_t max_lds) {
     return hipSuccess;
 }
 
-hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream) {
+hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream, const unsigned char* inline_tab,
+                        size_t inline_bytes) {
     const dim3 grid(c.blocks), block(c.waves_per_block * 64);
+    if (inline_tab) {
+        if (!a.sort_cand || a.jobs || inline_bytes > kInlineTableBytes) return hipErrorInvalidValue;
+        TraceArgsInline ai{};
+        static_cast<TraceArgs&>(ai) = a;
+        std::memcpy(ai.inline_tab, inline_tab, inline_bytes);
+        hipLaunchKernelGGL((trace_kernel<true, true, true>), grid, block, c.lds_bytes, stream, ai);
+        return hipGetLastError();
+    }
     if (a.sort_cand) {
         if (!a.jobs)
             hipLaunchKernelGGL((trace_kernel<true, true>), grid, block, c.lds_bytes, stream, a);

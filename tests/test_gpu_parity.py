@@ -260,6 +260,32 @@ def test_transform_updates_are_stream_ordered(ctx, torch_dev):
         parity.assert_parity(parity.compare(parity.to_numpy(hh), ref, ref.margin, rays))
 
 
+def test_small_scene_traces_keep_their_transforms_on_any_stream(ctx, torch_dev):
+    """A scene of at most 8 slots carries its frame table in the arguments of
+    the launches after a transform update: traces on two streams, each
+    enqueued after a different update and with no host wait, see their own
+    frame."""
+    torch = torch_dev
+    sc = S.fbm_terrain_d10()
+    rays, _ = sc.rays(W=160, H=90)
+    r = torch.from_numpy(rays).cuda()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    h = ctx.upload_scene(sc)
+    frames = (3, 17, 29, 44)
+    try:
+        torch.cuda.synchronize()
+        res = []
+        for i, f in enumerate(frames):
+            ctx.set_transforms(h, sc.xform(f))
+            res.append(ctx.trace(h, r, stream=streams[i % 2]))
+        torch.cuda.synchronize()
+    finally:
+        ctx.free_scene(h)
+    for f, hh in zip(frames, res):
+        ref = oracle.trace_scene(sc, rays, frame=f, margin=True)
+        parity.assert_parity(parity.compare(parity.to_numpy(hh), ref, ref.margin, rays))
+
+
 def test_rejected_transforms_change_nothing(ctx, torch_dev):
     """A call rejected for one slot's map (singular) stores none of its maps:
     a later call that uploads the table again still traces the old ones."""
