@@ -243,7 +243,9 @@ typedef struct {
    svo_trace_rays per job.  At most 256 non-empty jobs and 2047 frame
    records (1 + n_slots per job) per call; jobs with n == 0 are skipped.  The
    job table is packed on the host into pinned memory and copied on `stream`
-   (a ring of four tables; a fifth call waits for the first to finish). */
+   (a ring of four tables; a fifth call waits for the first to finish); a
+   single job of a scene of at most 8 slots instead takes its frame table in
+   the kernel arguments, with no copy. */
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
 
 /* Composite traced hits into an RGBA8 image (the colour field of the

@@ -1242,6 +1242,21 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         const size_t lds = fit_lds(ctx, a, cfg.waves_per_block);
         if (lds > ctx->max_lds) return fail(SVO_ERANGE, "batch needs %zu bytes of LDS per work-group", lds);
 
+        if (P.jobs.size() == 1 && P.jobs[0].S->inline_tab) {
+            // one job of a small scene: its table (the scene's layout, frame
+            // base 0) travels in the kernel arguments, with no table copy
+            const PackedJob& Q = P.jobs[0];
+            const Scene& S = *Q.S;
+            const svo_job& J = *Q.j;
+            a.jobs = nullptr;
+            a.job0 = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
+                                 J.out_normal, 0, 0, 0, Q.T.n_cand, a.lds_nodes, 0, Q.T.n_inline};
+            a.inline_off_cand = (uint32_t)cand_offset(S.n_frames);
+            a.inline_off_sph = (uint32_t)sphere_offset(S.n_frames, S.n_slots);
+            const unsigned char* tab = Q.table.empty() ? S.h_stage[S.cur] : Q.table.data();
+            return launch(ctx, cfg, a, st, tab, bvh_offset(S.n_frames, S.n_slots));
+        }
+
         auto& B = ctx->batch[ctx->next_batch];
         ctx->next_batch = (ctx->next_batch + 1) % 4;
         if (B.ev) HIP_TRY(hipEventSynchronize(B.ev));
