@@ -519,7 +519,7 @@ def main():
     if not args.no_c5:
         c5, c5_scene, c5_h = c5_throughput(ctx, max(5, K // 6))
         if args.serve_requests > 0:
-            c5_serving = serve_c5(ctx, c5_scene, c5_h, max(40, args.serve_requests // 10), 0.6)
+            c5_serving = serve_c5(ctx, c5_scene, c5_h, max(40, args.serve_requests // 5), 0.6)
         ctx.free_scene(c5_h)
         del c5_scene
     serving = None

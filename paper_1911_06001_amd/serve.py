@@ -221,7 +221,7 @@ def poisson_requests(n: int, rate: float, seed: int, scenes: List[str], frames: 
 
 class Server:
     def __init__(self, ctx: svo.Context, scenes: Dict[str, SceneEntry], hbm_budget: int,
-                 max_rays_per_step: int = 1 << 22, solo_rays_per_step: int = 1 << 24, inflight_steps: int = 2,
+                 max_rays_per_step: int = 1 << 23, solo_rays_per_step: int = 1 << 24, inflight_steps: int = 2,
                  keep_outputs: bool = False,
                  policy: str = "edf", graph: bool = False, max_jobs: int = 16, max_frames: int = 64):
         import torch
