@@ -334,7 +334,8 @@ int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
 /* Autotuner.  Times candidate kernel configurations on n device sample rays
    against `scene` under its current transforms, in two stages: the launch
    shape (waves per work-group, work-groups per CU, LDS pool-prefix size),
-   then lane refill and tiles per work-queue claim for the fastest shape.  Keeps
+   then lane refill and tiles per work-queue claim for the fastest shape,
+   then five times longer timings of that winner and the next two shapes.  Keeps
    the fastest for that scene -- later svo_trace_rays calls on it use it, and
    a batch uses it when that scene holds most of the batch's rays -- and
    writes it to *best (nullable).  Results never depend on the

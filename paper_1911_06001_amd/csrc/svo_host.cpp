@@ -1487,21 +1487,21 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     const svo_config was_cfg = S->cfg;
     svo_config win = base;
     float win_ms = 1e30f;
-    // Two stages: the launch shape (waves per work-group, work-groups per
-    // CU, LDS node cache) at whole-tile refill and 2-tile claims, then
-    // refill and claim size for the winning shape.
+    // Stages: the launch shape (waves per work-group, work-groups per CU,
+    // LDS node cache) at whole-tile refill and 2-tile claims; refill and
+    // claim size for the winning shape; a longer timing of the best three.
     static const uint32_t kWaves[] = {4, 8, 12, 16};
     static const uint32_t kBlocks[] = {1, 2, 3, 4, 5, 6, 8};
     static const uint32_t kCache[] = {1024, 2048, 4096};
     static const uint32_t kRefill[] = {0, 48};
     static const uint32_t kClaim[] = {1, 2, 4};
-    auto time_cand = [&](const svo_config& cand, float& ms) -> int {
+    auto time_cand = [&](const svo_config& cand, float& ms, int launches = 6) -> int {
         S->tuned = true;
         S->cfg = cand;
         int r = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
         if (r) return r;  // SVO_ERANGE: does not fit in LDS
         if (hipEventRecord(e0, st) != hipSuccess) return fail(SVO_EDEVICE, "tuner event record failed");
-        for (int k = 0; k < 6 && r == SVO_OK; ++k)
+        for (int k = 0; k < launches && r == SVO_OK; ++k)
             r = svo_trace_rays(ctx, scene, sample_rays, n, d_id, nullptr, d_t, nullptr, stream);
         if (r) return r;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1510,12 +1510,14 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
         return SVO_OK;
     };
     int rc = SVO_OK;
-    auto try_all = [&](const std::vector<svo_config>& cands) {
+    std::vector<std::pair<float, svo_config>> shapes;   // stage 1 timings
+    auto try_all = [&](const std::vector<svo_config>& cands, bool keep) {
         for (const svo_config& cand : cands) {
             float ms = 0.f;
             rc = time_cand(cand, ms);
             if (rc == SVO_ERANGE) continue;
             if (rc) return;
+            if (keep) shapes.push_back({ms, cand});
             if (ms < win_ms) {
                 win_ms = ms;
                 win = cand;
@@ -1536,7 +1538,7 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
                 cands.push_back(cand);
             }
         }
-    try_all(cands);
+    try_all(cands, true);
     if (rc == SVO_OK || rc == SVO_ERANGE) {
         const svo_config shape = win;
         cands.clear();
@@ -1548,7 +1550,28 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
                 cand.claim_tiles = y;
                 cands.push_back(cand);
             }
-        try_all(cands);
+        try_all(cands, false);
+    }
+    // Short timings are noisy: the winner and the next two shapes of the
+    // first stage are timed again with five times the launches, and the
+    // fastest of them is kept.
+    if ((rc == SVO_OK || rc == SVO_ERANGE) && win_ms < 1e30f) {
+        std::sort(shapes.begin(), shapes.end(), [](const std::pair<float, svo_config>& x,
+                                                   const std::pair<float, svo_config>& y) { return x.first < y.first; });
+        std::vector<svo_config> finalists{win};
+        for (size_t i = 0; i < shapes.size() && finalists.size() < 3; ++i)
+            if (std::memcmp(&shapes[i].second, &win, sizeof win) != 0) finalists.push_back(shapes[i].second);
+        float best_ms = 1e30f;
+        for (const svo_config& cand : finalists) {
+            float ms = 0.f;
+            rc = time_cand(cand, ms, 30);
+            if (rc == SVO_ERANGE) continue;
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                win = cand;
+            }
+        }
     }
     cleanup();
     if (rc && rc != SVO_ERANGE) {
