@@ -89,6 +89,7 @@ def cpu_baseline(scene, rays, frames, budget_s):
     bytes_sum = 0.0
     frame_list = []
     nnode = []
+    nnode_hi = []
     nframe = []
     f = 0
     while spent < budget_s and f < frames:
@@ -97,16 +98,20 @@ def cpu_baseline(scene, rays, frames, budget_s):
         spent += time.perf_counter() - t0
         done += rays.shape[0]
         # algorithmic bytes per ray: 8 B per node record, 64 B per frame
-        # record, 32 B ray in, 24 B hit out
+        # record, 32 B ray in, 24 B hit out; the node and frame counts are the
+        # oracle's lower bound (frames entered by the hit, each cut at it)
         bytes_sum += float((8.0 * h.nnode.astype(np.float64) + 64.0 * h.nframe + 32.0 + 24.0).sum())
         nnode.append(h.nnode)
+        nnode_hi.append(h.nnode_hi)
         nframe.append(h.nframe)
         frame_list.append(f)
         f += 1
     nn = np.concatenate(nnode) if nnode else np.zeros(1)
+    nh = np.concatenate(nnode_hi) if nnode_hi else np.zeros(1)
     nf = np.concatenate(nframe) if nframe else np.zeros(1)
     return dict(rays=done, seconds=spent, threads=threads, frames=frame_list, bytes_per_ray=bytes_sum / max(done, 1),
-                n_node_mean=float(nn.mean()), n_node_p99=float(np.percentile(nn, 99)), n_frame_mean=float(nf.mean()))
+                n_node_mean=float(nn.mean()), n_node_p99=float(np.percentile(nn, 99)), n_frame_mean=float(nf.mean()),
+                n_node_hi_mean=float(nh.mean()))
 
 
 def cpu_model() -> str:
@@ -531,6 +536,7 @@ def main():
                 "bytes_per_ray": round(bytes_per_ray, 2), "rays_per_launch": n,
                 "kernel_ms": round(kmean_a * 1e3, 4),
                 "n_node_mean": round(cb["n_node_mean"], 2), "n_node_p99": round(cb["n_node_p99"], 1),
+                "n_node_upper_mean": round(cb["n_node_hi_mean"], 2),
                 "n_frame_mean": round(cb["n_frame_mean"], 3)}
 
     ceilings = None

@@ -42,7 +42,8 @@ def lib():
         P = ctypes.c_void_p
         L.oracle_trace.restype = ctypes.c_int
         L.oracle_trace.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, P, ctypes.c_double, ctypes.c_uint32,
-                                   P, P, P, P, ctypes.c_uint64, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int]
+                                   P, P, P, P, ctypes.c_uint64, P, P, P, P, P, P, P, P, P, P,
+                                   ctypes.c_double, ctypes.c_int]
         L.oracle_trace_paper_form.restype = ctypes.c_int
         L.oracle_trace_paper_form.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, P, ctypes.c_double,
                                               ctypes.c_uint32, P, P, P, P, P, P, P, ctypes.c_uint64,
@@ -60,13 +61,21 @@ def _p(a):
 
 @dataclass
 class Hits:
+    """Oracle results per ray.  margin: the id margin (gaps that can change
+    which leaf is hit); margin_n: the normal margin (also the entry-face
+    gaps).  nnode / nframe: node records read and frames entered, lower bound
+    (frames entered by the final hit, each cut at it); nnode_hi / nframe_hi:
+    upper bound (every frame the segment meets, each to its own first hit)."""
     id: np.ndarray
     inst: np.ndarray
     t: np.ndarray
     normal: np.ndarray
     margin: Optional[np.ndarray] = None
+    margin_n: Optional[np.ndarray] = None
     nnode: Optional[np.ndarray] = None
     nframe: Optional[np.ndarray] = None
+    nnode_hi: Optional[np.ndarray] = None
+    nframe_hi: Optional[np.ndarray] = None
 
 
 def _scene_args(nodes, root, root_min, root_size, slot_child, slot_cell):
@@ -90,12 +99,16 @@ def trace(nodes, root, root_min, root_size, slot_child, slot_cell, fwd, rays, ma
     out = Hits(np.empty(n, np.uint32), np.empty(n, np.uint32), np.empty(n, np.float64), np.empty((n, 3), np.float64))
     if margin:
         out.margin = np.empty(n, np.float64)
+        out.margin_n = np.empty(n, np.float64)
     if counters:
         out.nnode = np.empty(n, np.uint32)
         out.nframe = np.empty(n, np.uint32)
+        out.nnode_hi = np.empty(n, np.uint32)
+        out.nframe_hi = np.empty(n, np.uint32)
     rc = lib().oracle_trace(_p(nodes), nodes.shape[0], int(root), _p(rmin), float(root_size), S, _p(sc), _p(cell),
                             _p(fw), _p(r), n, _p(out.id), _p(out.inst), _p(out.t), _p(out.normal), _p(out.margin),
-                            _p(out.nnode), _p(out.nframe), float(margin_eps), int(nthreads))
+                            _p(out.margin_n), _p(out.nnode), _p(out.nnode_hi), _p(out.nframe), _p(out.nframe_hi),
+                            float(margin_eps), int(nthreads))
     if rc != 0:
         raise ValueError("oracle_trace failed with %d" % rc)
     return out

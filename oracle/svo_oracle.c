@@ -230,7 +230,7 @@ static void hit_box(const oscene* sc, const ohit* best, double lo[3], double hi[
    whose entry lies beyond the best hit so far cannot improve it. */
 static void descend(const oscene* sc, int f, uint64_t cstart, unsigned mask, const double lo[3],
                     const double size[3], const double of[3], const double df[3], double tmin, double tmax,
-                    ohit* best, uint32_t* nnode)
+                    ohit* best)
 {
     ochild ch[8];
     int n = 0;
@@ -258,7 +258,6 @@ static void descend(const oscene* sc, int f, uint64_t cstart, unsigned mask, con
         if (c->te > best->t) break;
         if (c->idx >= sc->n_nodes) continue;
         uint64_t w = sc->nodes[c->idx];
-        if (nnode) ++*nnode;
         if (nd_is_xform(w)) continue;          /* belongs to another frame */
         if (nd_is_leaf(w)) {
             consider(best, c->te, inst, (uint32_t)c->idx, f, c->tn >= tmin ? c->axis : -1, c->tna, c->tn, c->tf,
@@ -266,7 +265,51 @@ static void descend(const oscene* sc, int f, uint64_t cstart, unsigned mask, con
             continue;
         }
         double csz[3] = {0.5 * size[0], 0.5 * size[1], 0.5 * size[2]};
-        descend(sc, f, nd_child_start(c->idx, w), nd_mask(w), c->lo, csz, of, df, tmin, tmax, best, nnode);
+        descend(sc, f, nd_child_start(c->idx, w), nd_mask(w), c->lo, csz, of, df, tmin, tmax, best);
+    }
+}
+
+/* ------------------------------------------------------------ node counts */
+
+/* Node records one frame's front-to-back descent reads before it stops: at
+   its own first solid leaf (that leaf included) or once the next cell is
+   entered beyond `bound`.  Cells are taken in entry order as in descend();
+   a transformed child is read (its record says it belongs to another frame)
+   and then skipped.  *found is set at the first leaf. */
+static void count_descend(const oscene* sc, uint64_t cstart, unsigned mask, const double lo[3],
+                          const double size[3], const double of[3], const double df[3], double tmin, double tmax,
+                          double bound, int* found, uint32_t* count)
+{
+    ochild ch[8];
+    int n = 0;
+    for (int i = 0; i < 8; ++i) {
+        if (!(mask & (1u << i))) continue;
+        ochild c;
+        for (int a = 0; a < 3; ++a) {
+            int bit = (i >> a) & 1;
+            double h = 0.5 * size[a];
+            c.lo[a] = bit ? lo[a] + h : lo[a];
+            c.hi[a] = bit ? lo[a] + size[a] : lo[a] + h;
+        }
+        if (!slab(of, df, c.lo, c.hi, &c.tn, &c.tf, c.tna, &c.axis)) continue;
+        c.te = c.tn > tmin ? c.tn : tmin;
+        c.tx = c.tf < tmax ? c.tf : tmax;
+        if (c.te > c.tx) continue;
+        c.oct = i;
+        c.idx = cstart + (uint64_t)popc8(mask & ((1u << i) - 1u));
+        ch[n++] = c;
+    }
+    sort_children(ch, n);
+    for (int k = 0; k < n && !*found; ++k) {
+        const ochild* c = &ch[k];
+        if (c->te > bound) return;
+        if (c->idx >= sc->n_nodes) continue;
+        uint64_t w = sc->nodes[c->idx];
+        ++*count;
+        if (nd_is_xform(w)) continue;
+        if (nd_is_leaf(w)) { *found = 1; return; }
+        double csz[3] = {0.5 * size[0], 0.5 * size[1], 0.5 * size[2]};
+        count_descend(sc, nd_child_start(c->idx, w), nd_mask(w), c->lo, csz, of, df, tmin, tmax, bound, found, count);
     }
 }
 
@@ -418,17 +461,55 @@ static double frame_scale(const double of[3], const double df[3], double t)
 
 typedef struct {
     uint32_t id, inst;
-    double t, n[3], margin;
-    uint32_t nnode, nframe;
+    double t, n[3];
+    double margin;      /* id margin: gaps that can change which leaf is hit (g1-g4) */
+    double margin_n;    /* normal margin: the id margin and the entry-face gaps (g4 at tmin, g5) */
+    uint32_t nnode_lo, nnode_hi, nframe_lo, nframe_hi;
 } oresult;
 
-static void trace_one(const oscene* sc, const float* ray, int want_margin, double margin_eps, oresult* res)
+/* Node records read per ray, as two bounds that do not depend on the order
+   in which an implementation visits frames.  Every frame whose root cell
+   the segment [tmin, tmax] meets is a frame entered; its root record counts
+   as one read, then its own front-to-back descent is counted (count_descend).
+     upper: every such frame, each descended to its own first hit;
+     lower: only frames entered no later than the final hit t*, each
+            descended to its own first hit or to t*, whichever comes first.
+   A front-to-back traversal that bounds each frame by its best hit so far
+   (never below t*) reads between the two; with one frame they coincide. */
+static void count_nodes(const oscene* sc, const double o[3], const double d[3], double tmin, double tmax,
+                        double tstar, oresult* res)
+{
+    for (int f = 0; f < sc->n_frames; ++f) {
+        const oframe* F = &sc->fr[f];
+        double of[3], df[3], hi[3], tn, tf, tna[3];
+        int ax;
+        map_ray(F->Wi, o, d, of, df);
+        for (int a = 0; a < 3; ++a) hi[a] = F->lo[a] + F->size[a];
+        if (!slab(of, df, F->lo, hi, &tn, &tf, tna, &ax)) continue;
+        double te = tn > tmin ? tn : tmin, tx = tf < tmax ? tf : tmax;
+        if (te > tx) continue;
+        uint32_t up = 1, lo = 1;
+        int found = 0;
+        if (!F->root_is_leaf) count_descend(sc, F->child, F->mask, F->lo, F->size, of, df, tmin, tmax, INFINITY, &found, &up);
+        res->nframe_hi++;
+        res->nnode_hi += up;
+        if (te > tstar) continue;
+        found = 0;
+        if (!F->root_is_leaf) count_descend(sc, F->child, F->mask, F->lo, F->size, of, df, tmin, tmax, tstar, &found, &lo);
+        res->nframe_lo++;
+        res->nnode_lo += lo;
+    }
+}
+
+static void trace_one(const oscene* sc, const float* ray, int want_margin, int want_counts, double margin_eps,
+                      oresult* res)
 {
     double o[3] = {ray[0], ray[1], ray[2]}, d[3] = {ray[4], ray[5], ray[6]};
     double tmin = ray[3], tmax = ray[7];
     res->id = ONONE; res->inst = ONONE; res->t = INFINITY;
     res->n[0] = res->n[1] = res->n[2] = 0.0;
-    res->margin = INFINITY; res->nnode = 0; res->nframe = 0;
+    res->margin = INFINITY; res->margin_n = INFINITY;
+    res->nnode_lo = res->nnode_hi = res->nframe_lo = res->nframe_hi = 0;
     for (int a = 0; a < 3; ++a)
         if (!isfinite(o[a]) || !isfinite(d[a])) return;
     if (isnan(tmin) || isnan(tmax) || tmin > tmax || tmin == INFINITY) return;
@@ -448,15 +529,13 @@ static void trace_one(const oscene* sc, const float* ray, int want_margin, doubl
         if (!slab(of, df, F->lo, hi, &tn, &tf, tna, &ax)) continue;
         double te = tn > tmin ? tn : tmin, tx = tf < tmax ? tf : tmax;
         if (te > tx) continue;
-        res->nframe++;
-        res->nnode++;  /* the frame root record */
         if (te > best.t) continue;
         uint32_t inst = F->slot < 0 ? ONONE : (uint32_t)F->slot;
         if (F->root_is_leaf) {
             consider(&best, te, inst, F->root_id, f, tn >= tmin ? ax : -1, tna, tn, tf, F->lo, hi);
             continue;
         }
-        descend(sc, f, F->child, F->mask, F->lo, F->size, of, df, tmin, tmax, &best, &res->nnode);
+        descend(sc, f, F->child, F->mask, F->lo, F->size, of, df, tmin, tmax, &best);
     }
 
     if (best.frame >= 0) {
@@ -473,9 +552,11 @@ static void trace_one(const oscene* sc, const float* ray, int want_margin, doubl
             res->n[0] = n0 / len; res->n[1] = n1 / len; res->n[2] = n2 / len;
         }
     }
+    if (want_counts) count_nodes(sc, o, d, tmin, tmax, best.t, res);
 
     if (!want_margin) return;
     omargin m;
+    double gn = INFINITY;   /* gaps that only decide the entry face (normal) */
     m.g = INFINITY; m.t_hit = best.t; m.hit_frame = best.frame; m.hit_id = best.id;
     if (best.frame >= 0) {
         const oframe* F = &sc->fr[best.frame];
@@ -487,16 +568,18 @@ static void trace_one(const oscene* sc, const float* ray, int want_margin, doubl
         hit_box(sc, &best, blo, bhi);
         double g = seg_box_depth(of, df, blo, bhi, tmin, tmax) / S;
         if (g < m.g) m.g = g;
-        if (isfinite(tmax)) { g = fabs(tmax - best.t) / S; if (g < m.g) m.g = g; }   /* g4 */
-        g = fabs(best.tn - tmin) / S;                          /* g4: entry vs tmin */
-        if (g < m.g) m.g = g;
+        if (isfinite(tmax)) { g = fabs(tmax - best.t) / S; if (g < m.g) m.g = g; }   /* g4: hit vs tmax */
+        /* g4 at tmin: entered through a face or starting inside the box; the
+           box, and so the id, is the same either way */
+        g = fabs(best.tn - tmin) / S;
+        if (g < gn) gn = g;
         if (best.axis >= 0) {                                  /* g5: entry-axis tie */
             double a1 = -INFINITY, a2 = -INFINITY;
             for (int a = 0; a < 3; ++a) {
                 double v = best.tn_axis[a];
                 if (v > a1) { a2 = a1; a1 = v; } else if (v > a2) a2 = v;
             }
-            if (isfinite(a2)) { g = (a1 - a2) / S; if (g < m.g) m.g = g; }
+            if (isfinite(a2)) { g = (a1 - a2) / S; if (g < gn) gn = g; }
         }
     }
     for (int f = 0; f < sc->n_frames; ++f) {
@@ -530,6 +613,7 @@ static void trace_one(const oscene* sc, const float* ray, int want_margin, doubl
         descend_margin(sc, f, F->child, F->mask, F->lo, F->size, of, df, tmin, tmax, eps, S, &m);
     }
     res->margin = m.g;
+    res->margin_n = gn < m.g ? gn : m.g;
 }
 
 /* ------------------------------------------------------------ scene setup */
@@ -622,11 +706,18 @@ done:
 
 static void free_scene(oscene* sc) { free(sc->fr); sc->fr = NULL; }
 
-static void run_rays(const oscene* sc, const float* rays, uint64_t n_rays, uint32_t* out_id, uint32_t* out_inst,
-                     double* out_t, double* out_n, double* out_margin, uint32_t* out_nnode, uint32_t* out_nframe,
-                     double margin_eps, int nthreads)
+typedef struct {
+    uint32_t *id, *inst;
+    double *t, *n, *margin, *margin_n;
+    uint32_t *nnode_lo, *nnode_hi, *nframe_lo, *nframe_hi;
+} oouts;
+
+static void run_rays(const oscene* sc, const float* rays, uint64_t n_rays, const oouts* out, double margin_eps,
+                     int nthreads)
 {
     if (!(margin_eps > 0.0)) margin_eps = 1e-6;
+    int want_margin = out->margin != NULL || out->margin_n != NULL;
+    int want_counts = out->nnode_lo || out->nnode_hi || out->nframe_lo || out->nframe_hi;
     int64_t n = (int64_t)n_rays;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -634,14 +725,17 @@ static void run_rays(const oscene* sc, const float* rays, uint64_t n_rays, uint3
 #endif
     for (int64_t i = 0; i < n; ++i) {
         oresult r;
-        trace_one(sc, rays + 8 * i, out_margin != NULL, margin_eps, &r);
-        if (out_id) out_id[i] = r.id;
-        if (out_inst) out_inst[i] = r.inst;
-        if (out_t) out_t[i] = r.t;
-        if (out_n) { out_n[3 * i] = r.n[0]; out_n[3 * i + 1] = r.n[1]; out_n[3 * i + 2] = r.n[2]; }
-        if (out_margin) out_margin[i] = r.margin;
-        if (out_nnode) out_nnode[i] = r.nnode;
-        if (out_nframe) out_nframe[i] = r.nframe;
+        trace_one(sc, rays + 8 * i, want_margin, want_counts, margin_eps, &r);
+        if (out->id) out->id[i] = r.id;
+        if (out->inst) out->inst[i] = r.inst;
+        if (out->t) out->t[i] = r.t;
+        if (out->n) { out->n[3 * i] = r.n[0]; out->n[3 * i + 1] = r.n[1]; out->n[3 * i + 2] = r.n[2]; }
+        if (out->margin) out->margin[i] = r.margin;
+        if (out->margin_n) out->margin_n[i] = r.margin_n;
+        if (out->nnode_lo) out->nnode_lo[i] = r.nnode_lo;
+        if (out->nnode_hi) out->nnode_hi[i] = r.nnode_hi;
+        if (out->nframe_lo) out->nframe_lo[i] = r.nframe_lo;
+        if (out->nframe_hi) out->nframe_hi[i] = r.nframe_hi;
     }
 }
 
@@ -650,23 +744,28 @@ static void run_rays(const oscene* sc, const float* rays, uint64_t n_rays, uint3
 /* First hits of n_rays rays (each 8 floats: ox oy oz tmin dx dy dz tmax).
    fwd: n_slots x 12 doubles, row-major 3x4 parent-relative forward maps;
    slot_cell: n_slots x 4 doubles (local root cell corner xyz, edge length).
-   Any output pointer may be NULL.  out_margin != NULL also computes the
-   grazing margin: the smallest t gap, relative to the frame's coordinate
-   scale, at which a perturbation could change the hit; only gaps below
-   margin_eps (<= 0 selects 1e-6) are resolved, larger ones read +inf.
-   Returns 0, -1 malformed pool, -2 out of memory, -3
-   singular transform. */
+   Any output pointer may be NULL.
+   out_margin / out_margin_n: grazing margins, the smallest t gap, relative to
+   the frame's coordinate scale, at which a perturbation of the ray could
+   change the hit leaf (id margin) or, in addition, its entry face (normal
+   margin); only gaps below margin_eps (<= 0 selects 1e-6) are resolved for
+   leaves other than the hit one, larger ones read +inf.
+   out_nnode_lo / _hi, out_nframe_lo / _hi: node records read and frames
+   entered, lower and upper bound (count_nodes).
+   Returns 0, -1 malformed pool, -2 out of memory, -3 singular transform. */
 int oracle_trace(const uint64_t* nodes, uint64_t n_nodes, uint32_t root, const double* root_min, double root_size,
                  uint32_t n_slots, const uint32_t* slot_child, const double* slot_cell, const double* fwd,
                  const float* rays, uint64_t n_rays, uint32_t* out_id, uint32_t* out_inst, double* out_t,
-                 double* out_n, double* out_margin, uint32_t* out_nnode, uint32_t* out_nframe, double margin_eps,
+                 double* out_n, double* out_margin, double* out_margin_n, uint32_t* out_nnode_lo,
+                 uint32_t* out_nnode_hi, uint32_t* out_nframe_lo, uint32_t* out_nframe_hi, double margin_eps,
                  int nthreads)
 {
     oscene sc;
     int rc = collect_frames(nodes, n_nodes, root, root_min, root_size, n_slots, slot_child, slot_cell, fwd, &sc);
     if (rc != 0) { free_scene(&sc); return rc; }
-    run_rays(&sc, rays, n_rays, out_id, out_inst, out_t, out_n, out_margin, out_nnode, out_nframe, margin_eps,
-             nthreads);
+    oouts out = {out_id, out_inst, out_t, out_n, out_margin, out_margin_n, out_nnode_lo, out_nnode_hi,
+                 out_nframe_lo, out_nframe_hi};
+    run_rays(&sc, rays, n_rays, &out, margin_eps, nthreads);
     free_scene(&sc);
     return 0;
 }
@@ -710,7 +809,8 @@ int oracle_trace_paper_form(const uint64_t* nodes, uint64_t n_nodes, uint32_t ro
             F->size[a] = sa * F->size[a];
         }
     }
-    run_rays(&sc, rays, n_rays, out_id, out_inst, out_t, out_n, NULL, NULL, NULL, 0.0, nthreads);
+    oouts out = {out_id, out_inst, out_t, out_n, NULL, NULL, NULL, NULL, NULL, NULL};
+    run_rays(&sc, rays, n_rays, &out, 0.0, nthreads);
     free_scene(&sc);
     return 0;
 }

@@ -408,10 +408,12 @@ def test_margin_flags_edge_rays(oracle_lib):
     ], np.float32)
     h = oracle.trace(i_leaf, 0, np.zeros(3), 8.0, np.zeros(0, np.uint32), np.zeros((0, 4)), np.zeros((0, 12)), rays,
                      margin=True)
-    assert h.margin[0] > 1e-6
+    assert h.margin[0] > 1e-6 and h.margin_n[0] > 1e-6
     assert h.margin[1] < 1e-6 and h.id[1] == 0
     assert h.margin[2] < 1e-6 and h.id[2] == NONE
-    assert h.margin[3] < 1e-6
+    # through the edge into the interior: one box either way, so the id is
+    # not in doubt, only the entry face (normal)
+    assert h.id[3] == 0 and h.margin[3] > 1e-6 and h.margin_n[3] < 1e-6
 
 
 def test_p6_closed_box_edge_contact_hits(oracle_lib):
