@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -114,6 +115,39 @@ def cpu_baseline(scene, rays, frames, budget_s):
                 n_node_hi_mean=float(nh.mean()))
 
 
+def replay_ceiling(ctx, handle, sc, fwd, rays, kc, n_cu, reps=5, max_cap=512):
+    """The trace's own ceiling: one frame traced by the counting build with a
+    trail of its node loads, then those loads replayed in order, with the
+    trace's dependence and grid and none of its arithmetic (plus each ray's
+    32-byte read and 24-byte write).  Returns the replay and trace times of
+    that frame (HIP events on the launch stream)."""
+    import torch
+    from paper_1911_06001_amd import ceiling
+    stream = torch.cuda.current_stream()
+    ctx.set_transforms(handle, fwd, stream=stream)
+    _, counts, _ = ctx.trace_counted(handle, rays)
+    c = counts.cpu().numpy().view(np.uint32)
+    loads = (c[0] - c[1]).astype(np.int64)
+    cap = int(min(loads.max(), max_cap))
+    _, counts, trail = ctx.trace_counted(handle, rays, trail_cap=cap)
+    nodes = torch.from_numpy(sc.nodes.view(np.int64)).cuda()
+    n = rays.shape[0]
+    out = torch.empty(6 * n, dtype=torch.int32, device=rays.device)
+    blocks, threads = n_cu * kc["blocks_per_cu"], 64 * kc["waves_per_block"]
+    sink = torch.empty(blocks * threads, dtype=torch.int64, device=rays.device)
+    n_lds = int(min(kc["lds_cache_nodes"], 16384, sc.nodes.shape[0]))
+    t_rep = ceiling._time(lambda: ceiling.replay(nodes, n_lds, trail, counts, rays, out, blocks, threads, sink,
+                                                 stream), reps)
+    hits = ctx.trace(handle, rays)
+    t_tr = ceiling._time(lambda: ctx.trace_into(handle, rays, hits.id, hits.t, hits.inst, hits.normal, stream=stream),
+                         reps)
+    del trail, nodes, out, sink
+    torch.cuda.empty_cache()
+    return {"replay_ms": round(t_rep * 1e3, 4), "trace_ms_same_frame": round(t_tr * 1e3, 4), "grid": [blocks, threads],
+            "lds_nodes": n_lds, "loads_per_ray_mean": round(float(loads.mean()), 3), "trail_cap": cap,
+            "loads_truncated": int(np.maximum(loads - cap, 0).sum())}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -202,7 +236,7 @@ def c5_throughput(ctx, steps, frames=60, knobs=None):
     w0 = time.perf_counter()
     for k in range(steps):
         e = ev[k]
-        ctx.set_transforms(h, xf[k % frames], stream=stream)
+        ctx.set_transforms(h, xf[(7 * k) % frames], stream=stream)   # 7 is coprime with the 60-frame cycle
         e[0].record(stream)
         ctx.trace_into(h, rays, prim.id, prim.t, prim.inst, prim.normal, stream=stream)
         e[1].record(stream)
@@ -418,8 +452,15 @@ def main():
         ctx.tune(stat, rays)
         log("tuned config", tuned)
 
+    # step k shows animation frame (stride * k) mod frames, stride coprime
+    # with the cycle: any number of steps samples the whole cycle evenly
+    stride = next(s for s in range(7, 7 + args.frames + 1) if math.gcd(s, args.frames) == 1)
+
+    def frame_of(k):
+        return (stride * k) % args.frames
+
     def step_anim(k):
-        ctx.set_transforms(anim, xf[k % args.frames], stream=stream)
+        ctx.set_transforms(anim, xf[frame_of(k)], stream=stream)
         ctx.trace_into(anim, rays, out_id, out_t, out_inst, out_n, stream=stream)
 
     def step_static(k):
@@ -431,7 +472,7 @@ def main():
         w0 = time.perf_counter()
         for k in range(K):
             if step is step_anim:
-                ctx.set_transforms(anim, xf[k % args.frames], stream=stream)
+                ctx.set_transforms(anim, xf[frame_of(k)], stream=stream)
                 evs[k][0].record(stream)
                 ctx.trace_into(anim, rays, out_id, out_t, out_inst, out_n, stream=stream)
                 evs[k][1].record(stream)
@@ -472,7 +513,7 @@ def main():
         for k in range(K):
             st = pipe_streams[k % 2]
             if animated:
-                ctx.set_transforms(handle, xf[k % args.frames], stream=st)
+                ctx.set_transforms(handle, xf[frame_of(k)], stream=st)
             o = pipe_out[k % 2]
             ctx.trace_into(handle, rays, o[0], o[1], o[2], o[3], stream=st)
         torch.cuda.synchronize()
@@ -545,10 +586,17 @@ def main():
         kc = tuned or cfg
         n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
         ceilings = ceiling.measure(int(sc.nodes.nbytes), n_cu * kc["blocks_per_cu"], 64 * kc["waves_per_block"])
+        rep = replay_ceiling(ctx, anim, sc, xf[0], rays, kc, n_cu)
+        ceilings["replay"] = rep
         log("ceilings", ceilings)
         if roof is not None:
+            # the replay ceiling: the same algorithmic bytes over the replay's time
+            ceilings["replay_GBps"] = round(bytes_per_ray * n / (rep["replay_ms"] * 1e-3) / 1e9, 1)
+            ceilings["frac_replay"] = round(rep["replay_ms"] / rep["trace_ms_same_frame"], 4)
             for k in ("gather_independent_GBps", "gather_dependent_GBps", "stream_pool_GBps", "stream_hbm_GBps"):
                 ceilings["frac_" + k[:-5]] = round(roof["achieved"] / ceilings[k], 4)
+            roof["target_ceiling"] = "replay"
+            roof["frac_of_target_ceiling"] = ceilings["frac_replay"]
 
     instances = None
     if not args.no_instances:

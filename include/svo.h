@@ -176,7 +176,8 @@ int svo_get_scene_stats(svo_ctx* ctx, svo_scene scene, svo_scene_stats* out);
    count).  fwd_3x4: host, count * 12 floats, row-major 3x4 [L | b] with
    x_parent = L x_local + b (paper Eq. 3 inverts this per frame; nested slots
    compose).  The library composes and inverts in FP64 on the host and packs
-   one 64-byte FP32 record per frame.  A scene of at most 8 slots carries
+   one 64-byte FP32 record per frame, plus its exact (FP64) map, from which
+   a hit's entry t and face are recomputed.  A scene of at most 10 slots carries
    that table to each trace in the kernel arguments: this call then does no
    device work, and every trace keeps the transforms current when it was
    enqueued, on any stream.  A larger scene's table is copied on `stream`;
@@ -201,6 +202,22 @@ int svo_set_transforms(svo_ctx* ctx, svo_scene scene, uint32_t first_slot, uint3
    overlap (each stream has its own work queue, up to 64 streams). */
 int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                    uint32_t* out_inst, float* out_t, float* out_normal, void* stream);
+
+/* Trace as svo_trace_rays in a counting build of the kernel, for tests and
+   measurement (the memory a traversal reads per node and per transform,
+   Sec. 5.2); results are identical to svo_trace_rays.  counts: device, 3 *
+   n uint32, zeroed by the caller: counts[i] = node records ray i read (each
+   frame walked counts its root record once, then every pool node the walk
+   loads), counts[n + i] = frames walked, counts[2n + i] += 1 per result
+   write (exactly 1 when every ray is claimed and written once).  trail:
+   nullable device uint32 array of trail_cap * n: trail[k * n + i] = pool
+   index of ray i's k-th node load for k < trail_cap, bit 31 set when it came
+   from the LDS copy of the pool prefix.  Errors: as svo_trace_rays;
+   SVO_EINVAL without counts, SVO_ERANGE above 2^31 - 1 rays or a trail over
+   2^40 entries. */
+int svo_trace_rays_counted(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                           uint32_t* out_inst, float* out_t, float* out_normal, uint32_t* counts, uint32_t* trail,
+                           uint32_t trail_cap, void* stream);
 
 /* Trace with the hit buffer of the previous frame (Sec. 4.3, applied to
    transforms on nodes): on entry the outputs hold the results of an
@@ -244,7 +261,7 @@ typedef struct {
    records (1 + n_slots per job) per call; jobs with n == 0 are skipped.  The
    job table is packed on the host into pinned memory and copied on `stream`
    (a ring of four tables; a fifth call waits for the first to finish); a
-   single job of a scene of at most 8 slots instead takes its frame table in
+   single job of a scene of at most 10 slots instead takes its frame table in
    the kernel arguments, with no copy. */
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
 

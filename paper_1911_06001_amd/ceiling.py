@@ -11,7 +11,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsvo_ceiling.so")
-EXPORTS = ("svo_ceiling_last_error", "svo_ceiling_gather", "svo_ceiling_stream")
+EXPORTS = ("svo_ceiling_last_error", "svo_ceiling_gather", "svo_ceiling_stream", "svo_ceiling_replay")
 
 _lib = None
 
@@ -30,6 +30,8 @@ def lib():
     L.svo_ceiling_gather.argtypes = [P, U64, U32, U32, U32, U32, U32, U64, P, P]
     L.svo_ceiling_stream.restype = I
     L.svo_ceiling_stream.argtypes = [P, U64, U32, U32, U32, P, P]
+    L.svo_ceiling_replay.restype = I
+    L.svo_ceiling_replay.argtypes = [P, U64, U32, P, P, U64, U32, P, P, U32, U32, P, P]
     _lib = L
     return L
 
@@ -57,6 +59,21 @@ def stream_read(buf, blocks: int, threads: int, reps: int, sink, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().svo_ceiling_stream(buf.data_ptr(), buf.numel() * buf.element_size(), blocks, threads, reps,
                                     sink.data_ptr(), st.cuda_stream))
+
+
+def replay(nodes, n_lds: int, trail, counts, rays, out, blocks: int, threads: int, sink, stream=None):
+    """Enqueue one replay of a counted trace's node loads (nodes: int64
+    device pool; trail [cap, n] and counts [3, n] int32 device tensors from
+    svo_trace_rays_counted; rays [n, 8] float32; out: int32 device tensor of
+    at least 6 n elements)."""
+    import torch
+    n = rays.shape[0]
+    cap = trail.shape[0] if trail is not None else 0
+    assert counts.shape == (3, n) and sink.numel() >= blocks * threads and out.numel() >= 6 * n
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().svo_ceiling_replay(nodes.data_ptr(), nodes.numel(), n_lds,
+                                    trail.data_ptr() if trail is not None else None, counts.data_ptr(), n, cap,
+                                    rays.data_ptr(), out.data_ptr(), blocks, threads, sink.data_ptr(), st.cuda_stream))
 
 
 def _time(fn, reps: int) -> float:

@@ -34,9 +34,12 @@ __device__ __forceinline__ T gload(const T* p, uint64_t i) {
 // index arithmetic, bound the kernel.
 // dependent = 0: the next state is a xorshift32 step of the previous one,
 //   so all loads of a thread can be in flight together (throughput).
-// dependent = 1: the next state is hashed from the word just loaded, so a
-//   stream has one load in flight at a time (latency; the octree walk has
-//   this shape: the next node address comes out of the last node).
+// dependent = 1: the next state is hashed from the word just loaded and
+//   the stream's own salt, so a stream has one load in flight at a time
+//   (latency; the octree walk has this shape: the next node address comes
+//   out of the last node).  The salt keeps streams apart: without it two
+//   streams that load the same word would follow one path from then on, and
+//   the streams would collapse onto a few cache-resident words.
 __device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
     x ^= x << 13;
     x ^= x >> 17;
@@ -49,10 +52,14 @@ __global__ __launch_bounds__(1024) void gather_kernel(const uint64_t* __restrict
                                                       uint32_t loads, uint32_t dependent, uint64_t seed,
                                                       uint64_t* __restrict__ sink) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t st[CHAINS];
+    uint32_t st[CHAINS], salt[CHAINS];
     uint64_t acc = 0;
 #pragma unroll
-    for (int c = 0; c < CHAINS; ++c) st[c] = (uint32_t)mix64(seed ^ (tid * CHAINS + c)) | 1u;
+    for (int c = 0; c < CHAINS; ++c) {
+        const uint64_t h = mix64(seed ^ (tid * CHAINS + c));
+        st[c] = (uint32_t)h | 1u;
+        salt[c] = (uint32_t)(h >> 32);
+    }
     for (uint32_t k = 0; k < loads; ++k) {
         uint64_t w[CHAINS];
 #pragma unroll
@@ -60,7 +67,8 @@ __global__ __launch_bounds__(1024) void gather_kernel(const uint64_t* __restrict
 #pragma unroll
         for (int c = 0; c < CHAINS; ++c) {
             acc ^= w[c];
-            st[c] = dependent ? (((uint32_t)w[c] ^ (uint32_t)(w[c] >> 32)) * 0x9E3779B1u + k) | 1u : xorshift32(st[c]);
+            st[c] = dependent ? (((uint32_t)w[c] ^ (uint32_t)(w[c] >> 32) ^ salt[c]) * 0x9E3779B1u + k) | 1u
+                              : xorshift32(st[c]);
         }
     }
     ((__attribute__((address_space(1))) uint64_t*)sink)[tid] = acc;
@@ -94,6 +102,54 @@ __global__ __launch_bounds__(1024) void stream_kernel(const v4u* __restrict__ bu
     ((__attribute__((address_space(1))) uint64_t*)sink)[tid] = ((uint64_t)(a0 ^ a1) << 32) | (a2 ^ a3);
 }
 
+// Replay of a trace's recorded memory traffic with none of its arithmetic:
+// each lane takes one ray (64 consecutive rays per wave, waves striding
+// over the 64-ray tiles), reads the ray (32 bytes), then, in order, the
+// node words its trace read -- trail[k n + g] for k below the ray's pool
+// reads (counts[g] - counts[n + g]) and cap, from the LDS copy of the pool
+// prefix when bit 31 is set (every work-group fills it first, as the trace
+// does) -- each load's address waiting on the word before it (the walk
+// decides its next step from the node it just read; dep_mask = 0 keeps the
+// addresses unchanged), and writes 24 bytes of result.
+__global__ __launch_bounds__(1024) void replay_kernel(const uint64_t* __restrict__ nodes, uint32_t n_nodes, uint32_t n_lds,
+                                                      const uint32_t* __restrict__ trail,
+                                                      const uint32_t* __restrict__ counts, uint64_t n, uint32_t cap,
+                                                      const v4u* __restrict__ rays, uint32_t* __restrict__ out,
+                                                      uint32_t dep_mask, uint64_t* __restrict__ sink) {
+    extern __shared__ uint64_t lds[];
+    for (uint32_t i = threadIdx.x; i < n_lds; i += blockDim.x) lds[i] = gload(nodes, i);
+    __syncthreads();
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t tiles = (n + 63) >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint64_t acc = 0;
+    for (uint64_t t = tid >> 6; t < tiles; t += waves) {
+        const uint64_t g = t * 64 + lane;
+        if (g >= n) continue;
+        const v4u r0 = gload(rays, 2 * g), r1 = gload(rays, 2 * g + 1);
+        uint32_t carry = r0.x ^ r0.y ^ r0.z ^ r0.w ^ r1.x ^ r1.y ^ r1.z ^ r1.w;
+        carry &= dep_mask;
+        const uint32_t reads = gload(counts, g) - gload(counts, n + g);
+        const uint32_t m = reads < cap ? reads : cap;
+        for (uint32_t k = 0; k < m; ++k) {
+            const uint32_t e = gload(trail, (uint64_t)k * n + g) ^ carry;
+            const uint32_t idx = e & 0x7FFFFFFFu;
+            const uint64_t w = (e >> 31) ? lds[idx < n_lds ? idx : 0] : gload(nodes, idx < n_nodes ? idx : 0);
+            acc ^= w;
+            carry = ((uint32_t)w ^ (uint32_t)(w >> 32)) & dep_mask;
+        }
+        __attribute__((address_space(1))) uint32_t* o = (__attribute__((address_space(1))) uint32_t*)out;
+        o[g] = (uint32_t)acc;                 // id
+        o[n + g] = (uint32_t)(acc >> 32);     // slot
+        o[2 * n + g] = m;                     // t
+        o[3 * n + 3 * g] = carry;             // normal
+        o[3 * n + 3 * g + 1] = carry;
+        o[3 * n + 3 * g + 2] = carry;
+    }
+    ((__attribute__((address_space(1))) uint64_t*)sink)[tid] = acc;
+}
+
 thread_local char g_err[256];
 
 int fail(int code, const char* msg) {
@@ -125,6 +181,22 @@ int svo_ceiling_gather(const uint64_t* buf, uint64_t n_words, uint32_t blocks, u
         default: return fail(SVO_CEILING_EINVAL, "chains must be 1, 2, 4 or 8");
     }
     return hipGetLastError() == hipSuccess ? 0 : fail(SVO_CEILING_EDEVICE, "gather launch failed");
+}
+
+int svo_ceiling_replay(const uint64_t* nodes, uint64_t n_nodes, uint32_t n_lds, const uint32_t* trail,
+                       const uint32_t* counts, uint64_t n, uint32_t cap, const float* rays, uint32_t* out,
+                       uint32_t blocks, uint32_t threads_per_block, uint64_t* sink, void* stream) {
+    if (!nodes || !counts || !rays || !out || !sink || (cap && !trail) || n == 0 || n_nodes == 0)
+        return fail(SVO_CEILING_EINVAL, "nodes, counts, rays, out, sink (and trail when cap > 0) and n are required");
+    if (n_lds > n_nodes || n_lds > 16384) return fail(SVO_CEILING_EINVAL, "n_lds must be at most n_nodes and 16384");
+    if (n_nodes > 0x7FFFFFFFull) return fail(SVO_CEILING_EINVAL, "n_nodes must be below 2^31");
+    if (((uintptr_t)rays) & 15u) return fail(SVO_CEILING_EINVAL, "rays must be 16-byte aligned");
+    if (blocks == 0 || threads_per_block == 0 || threads_per_block > 1024 || (threads_per_block & 63u))
+        return fail(SVO_CEILING_EINVAL, "threads_per_block must be a multiple of 64 in 64..1024");
+    hipLaunchKernelGGL(replay_kernel, dim3(blocks), dim3(threads_per_block), (size_t)n_lds * 8, (hipStream_t)stream,
+                       nodes, (uint32_t)n_nodes, n_lds, trail, counts, n, cap, reinterpret_cast<const v4u*>(rays), out,
+                       0u, sink);
+    return hipGetLastError() == hipSuccess ? 0 : fail(SVO_CEILING_EDEVICE, "replay launch failed");
 }
 
 int svo_ceiling_stream(const void* buf, uint64_t bytes, uint32_t blocks, uint32_t threads_per_block, uint32_t reps,

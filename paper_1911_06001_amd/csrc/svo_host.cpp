@@ -342,7 +342,7 @@ struct svo_plan {
     svo::TraceArgs args{};
     svo::LaunchCfg launch_cfg{};
     uint32_t max_jobs = 0, max_frames = 0, max_cand = 0, stack_cap = 1, nest_cap = 0, max_bvh = 0, bvh_depth_cap = 0;
-    size_t off_jobs = 0, off_frames = 0, off_cand = 0, off_sph = 0, off_bvh = 0, bytes = 0;
+    size_t off_jobs = 0, off_frames = 0, off_cand = 0, off_sph = 0, off_x = 0, off_bvh = 0, bytes = 0;
     unsigned char* dev = nullptr;
     unsigned char* host = nullptr;
     uint32_t* d_queue = nullptr;
@@ -403,14 +403,19 @@ Scene* find_scene(svo_ctx* ctx, svo_scene h) {
 }
 
 // Layout of a scene's frame table: n_frames records, then the candidate list
-// (n_slots u32), then one bounding sphere (centre xyz, radius) per record.
+// (n_slots u32), then one bounding sphere (centre xyz, radius) per record,
+// then one exact (FP64) map per record.
 inline size_t cand_offset(uint32_t n_frames) { return (size_t)n_frames * sizeof(svo::FrameRec); }
 inline size_t sphere_offset(uint32_t n_frames, uint32_t n_slots) {
     return (cand_offset(n_frames) + (size_t)n_slots * sizeof(uint32_t) + 15) & ~(size_t)15;
 }
+inline size_t xmap_offset(uint32_t n_frames, uint32_t n_slots) {
+    return sphere_offset(n_frames, n_slots) + (size_t)n_frames * 16;
+}
+constexpr size_t kXmapBytes = svo::kExactMapDoubles * sizeof(double);
 // ... then the hierarchy over the candidates (at most 2 n_slots nodes).
 inline size_t bvh_offset(uint32_t n_frames, uint32_t n_slots) {
-    return sphere_offset(n_frames, n_slots) + (size_t)n_frames * 16;
+    return xmap_offset(n_frames, n_slots) + (size_t)n_frames * kXmapBytes;
 }
 inline uint32_t bvh_capacity(uint32_t n_slots) { return std::max<uint32_t>(1, 2 * n_slots); }
 inline size_t table_size(uint32_t n_frames, uint32_t n_slots) {
@@ -500,6 +505,7 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
     svo::FrameRec* rec = reinterpret_cast<svo::FrameRec*>(out);
     uint32_t* cand = reinterpret_cast<uint32_t*>(out + cand_offset(S.n_frames));
     float* sph = reinterpret_cast<float*>(out + sphere_offset(S.n_frames, S.n_slots));
+    double* xm = reinterpret_cast<double*>(out + xmap_offset(S.n_frames, S.n_slots));
     std::memset(out, 0, S.table_bytes);
     T = TableInfo();
     // world
@@ -507,8 +513,9 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
     const uint32_t K0 = A.world_height;
     const double g0 = std::ldexp(1.0, (int)K0) / (double)S.root_size;
     for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c) W.m[4 * r + c] = (r == c) ? (float)g0 : 0.0f;
-        W.m[4 * r + 3] = (float)(-(double)S.root_min[r] * g0);
+        for (int c = 0; c < 3; ++c) xm[4 * r + c] = (r == c) ? g0 : 0.0;
+        xm[4 * r + 3] = -(double)S.root_min[r] * g0;
+        for (int c = 0; c < 4; ++c) W.m[4 * r + c] = (float)xm[4 * r + c];
     }
     W.inst = SVO_NONE;
     W.root = S.root;
@@ -537,9 +544,11 @@ int build_frames(const Scene& S, const std::vector<Aff>& fwd, unsigned char* out
         const uint32_t K = A.slot_height[s];
         const double g = std::ldexp(1.0, (int)K) / (double)cell[3];
         svo::FrameRec& F = rec[1 + s];
+        double* X = xm + (size_t)svo::kExactMapDoubles * (1 + s);
         for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c) F.m[4 * r + c] = (float)(g * inv.m[r][c]);
-            F.m[4 * r + 3] = (float)(g * (inv.m[r][3] - (double)cell[r]));
+            for (int c = 0; c < 3; ++c) X[4 * r + c] = g * inv.m[r][c];
+            X[4 * r + 3] = g * (inv.m[r][3] - (double)cell[r]);
+            for (int c = 0; c < 4; ++c) F.m[4 * r + c] = (float)X[4 * r + c];
         }
         F.child = S.slot_child[s];
         F.info = A.slot_mask[s] | (K << svo::FR_K_SHIFT);
@@ -792,7 +801,7 @@ int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t r
         S->n_frames = 1 + n_slots;
         S->table_bytes = table_size(S->n_frames, n_slots);
         // at most 16 slots: every candidate takes the sorted path, which
-        // needs no hierarchy, so records, candidates and spheres suffice
+        // needs no hierarchy, so records, candidates, spheres and exact maps suffice
         S->inline_tab = n_slots <= svo::kMaxSortedCand && bvh_offset(S->n_frames, n_slots) <= svo::kInlineTableBytes;
         const size_t fb = S->table_bytes;
         for (int k = 0; k < 2; ++k) {
@@ -989,7 +998,8 @@ int launch(svo_ctx* ctx, const svo_config& cfg, svo::TraceArgs& a, hipStream_t s
     const uint64_t cap = (uint64_t)ctx->n_cu * resident_blocks(ctx, c, lds);
     L.blocks = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
     L.lds_bytes = lds;
-    const hipError_t e = svo::launch_trace(a, L, st, inline_tab, inline_bytes);
+    const hipError_t e = a.counts ? svo::launch_trace_counted(a, L, st, inline_tab, inline_bytes)
+                                  : svo::launch_trace(a, L, st, inline_tab, inline_bytes);
     if (e != hipSuccess) return fail(SVO_EDEVICE, "trace launch failed: %s", hipGetErrorString(e));
     return SVO_OK;
 }
@@ -1074,11 +1084,11 @@ int pack_jobs(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, const std::set
 }
 
 // Write job records, frame records, candidates (absolute frame indices),
-// spheres and hierarchy nodes (skipped when br is null: launches that take
-// every candidate through the sorted path) of a packing into host memory;
-// the jobs of the cached pool get `cache_nodes` LDS nodes.
-void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t* cr, float* sr, svo::BvhNode* br,
-                  uint32_t cache_nodes) {
+// spheres, exact maps and hierarchy nodes (skipped when br is null: launches
+// that take every candidate through the sorted path) of a packing into host
+// memory; the jobs of the cached pool get `cache_nodes` LDS nodes.
+void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t* cr, float* sr, double* xr,
+                  svo::BvhNode* br, uint32_t cache_nodes) {
     uint64_t begin = 0;
     for (size_t i = 0; i < P.jobs.size(); ++i) {
         const PackedJob& Q = P.jobs[i];
@@ -1086,6 +1096,8 @@ void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t
         const unsigned char* tab = Q.table.empty() ? S.h_stage[S.cur] : Q.table.data();
         std::memcpy(fr + Q.frame_base, tab, (size_t)S.n_frames * sizeof(svo::FrameRec));
         std::memcpy(sr + 4 * (size_t)Q.frame_base, tab + sphere_offset(S.n_frames, S.n_slots), (size_t)S.n_frames * 16);
+        std::memcpy(xr + (size_t)svo::kExactMapDoubles * Q.frame_base, tab + xmap_offset(S.n_frames, S.n_slots),
+                    (size_t)S.n_frames * kXmapBytes);
         const uint32_t* sc = reinterpret_cast<const uint32_t*>(tab + cand_offset(S.n_frames));
         for (uint32_t c = 0; c < Q.T.n_cand + Q.T.n_inline; ++c) cr[Q.cand_base + c] = Q.frame_base + sc[c];
         if (br)
@@ -1123,7 +1135,8 @@ extern "C" {
 namespace {
 
 int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id, uint32_t* out_inst,
-               float* out_t, float* out_normal, void* stream, bool reuse, unsigned long long* retraced) {
+               float* out_t, float* out_normal, void* stream, bool reuse, unsigned long long* retraced,
+               uint32_t* counts = nullptr, uint32_t* trail = nullptr, uint32_t trail_cap = 0) {
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     Scene* S = find_scene(ctx, scene);
     if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
@@ -1145,6 +1158,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     a.frames = reinterpret_cast<const svo::FrameRec*>(S->d_table[S->cur]);
     a.cand = reinterpret_cast<const uint32_t*>(S->d_table[S->cur] + cand_offset(S->n_frames));
     a.spheres = reinterpret_cast<const float4*>(S->d_table[S->cur] + sphere_offset(S->n_frames, S->n_slots));
+    a.xmaps = reinterpret_cast<const double*>(S->d_table[S->cur] + xmap_offset(S->n_frames, S->n_slots));
     a.bvh = reinterpret_cast<const svo::BvhNode*>(S->d_table[S->cur] + bvh_offset(S->n_frames, S->n_slots));
     // the hierarchy is walked only past kMaxSortedCand candidates
     a.n_bvh_total = S->n_cand > svo::kMaxSortedCand ? S->n_bvh : 0u;
@@ -1158,6 +1172,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
         tab_bytes = bvh_offset(S->n_frames, S->n_slots);
         a.inline_off_cand = (uint32_t)cand_offset(S->n_frames);
         a.inline_off_sph = (uint32_t)sphere_offset(S->n_frames, S->n_slots);
+        a.inline_off_x = (uint32_t)xmap_offset(S->n_frames, S->n_slots);
     }
     a.n_jobs = 1;
     a.n_frames = S->n_frames;
@@ -1173,6 +1188,9 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     fill_common(cfg, a);
     a.reuse = reuse ? 1u : 0u;
     a.retraced = retraced;
+    a.counts = counts;
+    a.trail = trail;
+    a.trail_cap = trail ? trail_cap : 0u;
     return launch(ctx, cfg, a, st, tab, tab_bytes);
 }
 
@@ -1185,6 +1203,16 @@ int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n,
     return trace_rays(ctx, scene, rays, n, out_id, out_inst, out_t, out_normal, stream, false, nullptr);
 }
 
+int svo_trace_rays_counted(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
+                           uint32_t* out_inst, float* out_t, float* out_normal, uint32_t* counts, uint32_t* trail,
+                           uint32_t trail_cap, void* stream) {
+    if (n && !counts) return fail(SVO_EINVAL, "counts is required");
+    if (n > 0x7FFFFFFFull) return fail(SVO_ERANGE, "at most 2^31 - 1 rays per counted trace");
+    if (trail && (uint64_t)trail_cap * n > (1ull << 40)) return fail(SVO_ERANGE, "trail_cap * n is too large");
+    return trace_rays(ctx, scene, rays, n, out_id, out_inst, out_t, out_normal, stream, false, nullptr, counts,
+                      trail, trail_cap);
+}
+
 int svo_trace_rays_reuse(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                          uint32_t* out_inst, float* out_t, float* out_normal, uint64_t* retraced, void* stream) {
     if (n && !out_inst) return fail(SVO_EINVAL, "out_inst is required to reuse previous hits");
@@ -1192,7 +1220,12 @@ int svo_trace_rays_reuse(svo_ctx* ctx, svo_scene scene, const float* rays, uint6
                       reinterpret_cast<unsigned long long*>(retraced));
 }
 
-int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// svo_trace_batch.
+int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     if (n_jobs && !jobs) return fail(SVO_EINVAL, "jobs is NULL");
     try {
@@ -1205,6 +1238,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         uint32_t qslot;
         rc = queue_slot(ctx, st, qslot);
         if (rc) return rc;
+        uint32_t* queue = ctx->d_queue + svo::kQueueWords * qslot;
         HIP_TRY(hipSetDevice(ctx->device));
 
         // configuration and node cache: the pool with the most rays in this batch
@@ -1217,11 +1251,12 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
             }
         svo_config cfg = *pcfg;
 
-        // pack [jobs][frames][candidates][spheres][hierarchy nodes]
+        // pack [jobs][frames][candidates][spheres][exact maps][hierarchy nodes]
         const size_t jb = P.jobs.size() * sizeof(svo::JobRec);
         const size_t fb = (size_t)P.frames * sizeof(svo::FrameRec);
         const size_t sb = (jb + fb + (size_t)P.cands * sizeof(uint32_t) + 15) & ~(size_t)15;
-        const size_t bb = sb + (size_t)P.frames * 16;
+        const size_t xb = sb + (size_t)P.frames * 16;
+        const size_t bb = xb + (size_t)P.frames * kXmapBytes;
         const size_t bytes = bb + (size_t)P.bvh * sizeof(svo::BvhNode);
         svo::TraceArgs a{};
         a.n_bvh_total = P.max_cand > svo::kMaxSortedCand ? P.bvh : 0u;
@@ -1232,7 +1267,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         a.max_cand = P.max_cand;
         a.n_rays = P.total;
         a.cache_src = P.cache_src;
-        a.queue = ctx->d_queue + svo::kQueueWords * qslot;
+        a.queue = queue;
         a.lds_nodes = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, cache_pool_nodes) & ~1u;
         a.sort_cand = P.max_cand <= svo::kMaxSortedCand ? 1u : 0u;
         a.stack_levels = P.stack_levels;
@@ -1253,6 +1288,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
                                  J.out_normal, 0, 0, 0, Q.T.n_cand, a.lds_nodes, 0, Q.T.n_inline};
             a.inline_off_cand = (uint32_t)cand_offset(S.n_frames);
             a.inline_off_sph = (uint32_t)sphere_offset(S.n_frames, S.n_slots);
+            a.inline_off_x = (uint32_t)xmap_offset(S.n_frames, S.n_slots);
             const unsigned char* tab = Q.table.empty() ? S.h_stage[S.cur] : Q.table.data();
             return launch(ctx, cfg, a, st, tab, bvh_offset(S.n_frames, S.n_slots));
         }
@@ -1274,7 +1310,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         if (!B.ev) HIP_TRY(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
         write_tables(P, reinterpret_cast<svo::JobRec*>(B.host), reinterpret_cast<svo::FrameRec*>(B.host + jb),
                      reinterpret_cast<uint32_t*>(B.host + jb + fb), reinterpret_cast<float*>(B.host + sb),
-                     reinterpret_cast<svo::BvhNode*>(B.host + bb), a.lds_nodes);
+                     reinterpret_cast<double*>(B.host + xb), reinterpret_cast<svo::BvhNode*>(B.host + bb), a.lds_nodes);
         a.jobs = reinterpret_cast<const svo::JobRec*>(B.dev);
         if (P.jobs.size() == 1) {
             // one job: passed in the arguments, which selects the single-job
@@ -1285,6 +1321,7 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
         a.frames = reinterpret_cast<const svo::FrameRec*>(B.dev + jb);
         a.cand = reinterpret_cast<const uint32_t*>(B.dev + jb + fb);
         a.spheres = reinterpret_cast<const float4*>(B.dev + sb);
+        a.xmaps = reinterpret_cast<const double*>(B.dev + xb);
         a.bvh = reinterpret_cast<const svo::BvhNode*>(B.dev + bb);
         HIP_TRY(hipMemcpyAsync(B.dev, B.host, bytes, hipMemcpyHostToDevice, st));
         rc = launch(ctx, cfg, a, st);
@@ -1296,6 +1333,14 @@ int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* st
     } catch (const std::bad_alloc&) {
         return fail(SVO_ENOMEM, "out of host memory");
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
+    return trace_batch(ctx, jobs, n_jobs, stream);
 }
 
 // ------------------------------------------------------------------ plans
@@ -1328,12 +1373,13 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         pl->max_jobs = limits->max_jobs;
         pl->max_frames = limits->max_frames;
         pl->max_cand = std::min(max_slots, limits->max_frames);
-        // table layout: [header][jobs][frames][candidates][spheres], capacities
+        // table layout: [header][jobs][frames][candidates][spheres][exact maps][hierarchy], capacities
         pl->off_jobs = sizeof(svo::LaunchHdr);
         pl->off_frames = pl->off_jobs + (size_t)pl->max_jobs * sizeof(svo::JobRec);
         pl->off_cand = pl->off_frames + (size_t)pl->max_frames * sizeof(svo::FrameRec);
         pl->off_sph = (pl->off_cand + (size_t)pl->max_frames * sizeof(uint32_t) + 15) & ~(size_t)15;
-        pl->off_bvh = pl->off_sph + (size_t)pl->max_frames * 16;
+        pl->off_x = pl->off_sph + (size_t)pl->max_frames * 16;
+        pl->off_bvh = pl->off_x + (size_t)pl->max_frames * kXmapBytes;
         pl->max_bvh = pl->max_cand > svo::kMaxSortedCand ? 2 * pl->max_frames : 0u;
         pl->bvh_depth_cap = bvh_levels(pl->max_cand);
         pl->bytes = pl->off_bvh + (size_t)pl->max_bvh * sizeof(svo::BvhNode);
@@ -1378,6 +1424,7 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         a.frames = reinterpret_cast<const svo::FrameRec*>(pl->dev + pl->off_frames);
         a.cand = reinterpret_cast<const uint32_t*>(pl->dev + pl->off_cand);
         a.spheres = reinterpret_cast<const float4*>(pl->dev + pl->off_sph);
+        a.xmaps = reinterpret_cast<const double*>(pl->dev + pl->off_x);
         a.bvh = reinterpret_cast<const svo::BvhNode*>(pl->dev + pl->off_bvh);
         a.queue = pl->d_queue;
         *out = pl.get();
@@ -1423,7 +1470,7 @@ int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_
         std::memcpy(H, &hdr, sizeof hdr);
         write_tables(P, reinterpret_cast<svo::JobRec*>(H + plan->off_jobs), reinterpret_cast<svo::FrameRec*>(H + plan->off_frames),
                      reinterpret_cast<uint32_t*>(H + plan->off_cand), reinterpret_cast<float*>(H + plan->off_sph),
-                     plan->max_bvh ? reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh) : nullptr, fill);
+                     reinterpret_cast<double*>(H + plan->off_x), plan->max_bvh ? reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh) : nullptr, fill);
         return SVO_OK;
     } catch (const std::bad_alloc&) {
         return fail(SVO_ENOMEM, "out of host memory");

@@ -102,12 +102,17 @@ struct alignas(16) LaunchHdr {
 static_assert(sizeof(LaunchHdr) == 64, "launch header must be 64 bytes");
 
 // A one-job launch of a small scene whose transforms changed since its last
-// upload carries the frame table (records, candidates, spheres; no
-// hierarchy) in its kernel arguments (TraceArgsInline): no copy and no event
-// per transform update, and the launch keeps the transforms it was enqueued
-// with.  Larger arguments cost every launch a little, so launches that can
-// read an up-to-date device table keep the plain arguments.
-constexpr uint32_t kInlineTableBytes = 768;
+// upload carries the frame table (records, candidates, spheres, exact maps;
+// no hierarchy) in its kernel arguments (TraceArgsInline): no copy and no
+// event per transform update, and the launch keeps the transforms it was
+// enqueued with.  Larger arguments cost every launch a little, so launches
+// that can read an up-to-date device table keep the plain arguments.
+constexpr uint32_t kInlineTableBytes = 2048;
+
+// The exact map of a frame: the FrameRec map before rounding to FP32 (FP64,
+// rows r = 0..2 at [4r..4r+2], translation at [4r+3]).  The walk runs on the
+// FP32 record; the entry t of the cell it hits is recomputed from this one.
+constexpr uint32_t kExactMapDoubles = 12;
 
 // In a plan launch (hdr != nullptr) n_jobs, n_frames, n_cand_total,
 // n_bvh_total and lds_nodes are capacities that size the LDS layout, and the header holds
@@ -119,6 +124,7 @@ struct TraceArgs {
     const FrameRec* frames;   // n_frames records; job j's slot s is frames[frame_base_j + 1 + s]
     const uint32_t* cand;     // candidate frames (absolute indices), per job contiguous
     const float4* spheres;    // n_frames world bounding spheres (centre, radius) of the moved root cells
+    const double* xmaps;      // n_frames exact maps (kExactMapDoubles each), indexed like frames
     const BvhNode* bvh;       // n_bvh_total hierarchy nodes, per job contiguous (job j's root at bvh_base_j)
     uint32_t n_bvh_total;
     uint32_t bvh_depth;       // hierarchy stack entries per lane (used when sort_cand == 0)
@@ -139,9 +145,19 @@ struct TraceArgs {
     unsigned long long* retraced;  // reuse: rays traced again are added here (nullable)
     uint64_t tile_stride;     // claim i covers tile (i * tile_stride) mod tiles (coprime: a permutation)
     uint32_t step_limit;
-    // TraceArgsInline launches: frames, cand and spheres are read from the
-    // inline table at these byte offsets instead of the pointers above
-    uint32_t inline_off_cand, inline_off_sph;
+    // TraceArgsInline launches: frames, cand, spheres and exact maps are read
+    // from the inline table at these byte offsets instead of the pointers above
+    uint32_t inline_off_cand, inline_off_sph, inline_off_x;
+    // Counting launches (an instantiation of their own; ignored by the
+    // others), per launch-wide ray index g of n_rays: counts[g] node records
+    // read (each frame walked counts its root record), counts[n_rays + g]
+    // frames walked, counts[2 n_rays + g] result writes (added atomically:
+    // 1 when every ray is written exactly once); with trail, the index of
+    // the k-th node record read, trail[k n_rays + g] for k < trail_cap, bit
+    // 31 set when it came from the LDS copy of the pool prefix.
+    uint32_t* counts;
+    uint32_t* trail;
+    uint32_t trail_cap;
 };
 
 struct TraceArgsInline : TraceArgs {
@@ -203,5 +219,8 @@ hipError_t prepare_trace(size_t max_lds);
 // kInlineTableBytes; one-job launches with sorted candidates only).
 hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream,
                         const unsigned char* inline_tab = nullptr, size_t inline_bytes = 0);
+// The counting instantiation (a.counts set; single-job launches only).
+hipError_t launch_trace_counted(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream,
+                                const unsigned char* inline_tab = nullptr, size_t inline_bytes = 0);
 
 }  // namespace svo

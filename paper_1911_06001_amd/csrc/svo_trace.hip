@@ -20,7 +20,10 @@
 //      the best hit (the depth sort of Sec. 4.2): up to 16 in order of exact
 //      root-cell entry after the bounding-sphere test of Sec. 4.1, more
 //      through a hierarchy of their world boxes, nearer boxes first;
-//   6. write id, slot, t and the normal (entry face, inverse transpose).
+//   6. at the hit, recompute its entry t and face from the frame's FP64 map
+//      (the walk's FP32 entry t carries an error that grows with the
+//      coordinates); write id, slot, t and the normal (entry face, inverse
+//      transpose).
 //
 // Work distribution: a persistent grid.  Each wave keeps 64 rays in flight
 // and refills lanes once `refill` of them are idle (64 = whole tiles), from
@@ -49,6 +52,7 @@ constexpr uint32_t kXform = 0x80000000u;
 
 enum : uint32_t { M_DONE = 0, M_WALK = 1, M_SELECT = 2 };
 enum : uint32_t { EV_NONE = 0, EV_HIT = 1, EV_ENTER = 2, EV_END = 3, EV_LIMIT = 4 };
+enum : uint32_t { PEND_RESUME = 1, PEND_ROOT_HIT = 2 };
 
 struct Ray {
     float ox, oy, oz, tmin, dx, dy, dz, tmax;
@@ -78,10 +82,12 @@ __device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
 // Map the ray into frame F and clip it to the root cell [0, 2^K)^3 and
-// [tmin, tlimit].  Returns false when that interval is empty.  eaxis = axis
-// of the entry face, 3 when the ray starts inside (t0 = tmin).
-__device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, float tlimit, FrameRay& fr, float& t0,
-                                            int& eaxis) {
+// [tmin, tlimit].  Returns false when that interval is empty.  kPrecise:
+// the plane parameters take correctly rounded reciprocals (a walk runs on
+// them, and the error of every plane crossing it compares includes theirs);
+// otherwise the hardware reciprocal (entry tests that only order or cull).
+template <bool kPrecise>
+__device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, float tlimit, FrameRay& fr, float& t0) {
     const float gx = fmaf(F.m[0], r.ox, fmaf(F.m[1], r.oy, fmaf(F.m[2], r.oz, F.m[3])));
     const float gy = fmaf(F.m[4], r.ox, fmaf(F.m[5], r.oy, fmaf(F.m[6], r.oz, F.m[7])));
     const float gz = fmaf(F.m[8], r.ox, fmaf(F.m[9], r.oy, fmaf(F.m[10], r.oz, F.m[11])));
@@ -97,23 +103,82 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
     if (fabsf(dy) < eps) dy = copysignf(eps, dy);
     if (fabsf(dz) < eps) dz = copysignf(eps, dz);
     fr.flip = (dx < 0.f ? 1u : 0u) | (dy < 0.f ? 2u : 0u) | (dz < 0.f ? 4u : 0u);
-    fr.ix = rcp_fast(fabsf(dx));
-    fr.iy = rcp_fast(fabsf(dy));
-    fr.iz = rcp_fast(fabsf(dz));
+    if constexpr (kPrecise) {
+        fr.ix = 1.0f / fabsf(dx);
+        fr.iy = 1.0f / fabsf(dy);
+        fr.iz = 1.0f / fabsf(dz);
+    } else {
+        fr.ix = rcp_fast(fabsf(dx));
+        fr.iy = rcp_fast(fabsf(dy));
+        fr.iz = rcp_fast(fabsf(dz));
+    }
     fr.bx = -((dx < 0.f) ? (N - gx) : gx) * fr.ix;
     fr.by = -((dy < 0.f) ? (N - gy) : gy) * fr.iy;
     fr.bz = -((dz < 0.f) ? (N - gz) : gz) * fr.iz;
     fr.K = K;
     // root entry: the low mirrored planes are at 0, so t(0) = bias
     float te = max3f(fr.bx, fr.by, fr.bz);
-    eaxis = (fr.bx >= fr.by && fr.bx >= fr.bz) ? 0 : ((fr.by >= fr.bz) ? 1 : 2);
     const float tx = min3f(fmaf(N, fr.ix, fr.bx), fmaf(N, fr.iy, fr.by), fmaf(N, fr.iz, fr.bz));
-    if (te < r.tmin) {
-        te = r.tmin;
-        eaxis = 3;
-    }
+    if (te < r.tmin) te = r.tmin;
     t0 = te;
     return te <= fminf(tx, tlimit);
+}
+
+// The hit the walk found, checked and measured in FP64.  The walk decides
+// in FP32 which cell the ray meets first; its plane crossings carry an
+// error that grows with the coordinates (frame map, reciprocal direction,
+// rounding at the scale of t), so near an edge or a corner it may take a
+// cell the ray passes by, and its entry t is off by that much.  Here the
+// cell [p, p + size)^3 (p in frame F's mirrored grid coordinates) is
+// intersected with the ray mapped by F's exact map X in FP64 (Eq. 2: the
+// frame's ray keeps the world t): per axis the closed slab between the
+// cell's two face planes.  Returns whether max(t_near, tmin) <= min(t_far,
+// tmax) holds in FP64; then t = max(t_near, tmin) and axis = the entry face
+// (the largest t_near, ties to the lowest axis), 3 when the ray starts
+// inside the cell (t = tmin).
+__device__ __forceinline__ bool exact_hit(const double* X, const Ray& r, const FrameRay& fr, uint32_t px,
+                                          uint32_t py, uint32_t pz, uint32_t size, float& t, int& axis) {
+    const double N = (double)(1ull << fr.K), S = (double)size;
+    double tn = -INFINITY, tf = INFINITY;
+    int ea = 3;
+    // one axis at a time: a row's four doubles are the only FP64 values live
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        const double* row = X + 4 * k;
+        const double go = fma(row[0], (double)r.ox, fma(row[1], (double)r.oy, fma(row[2], (double)r.oz, row[3])));
+        const double gd = fma(row[0], (double)r.dx, fma(row[1], (double)r.dy, row[2] * (double)r.dz));
+        const uint32_t pk = (k == 0) ? px : ((k == 1) ? py : pz);
+        const double lo = ((fr.flip >> k) & 1u) ? N - (double)pk - S : (double)pk;
+        const double hi = lo + S;
+        double a, b;
+        if (gd == 0.0) {
+            // parallel: the whole line or nothing
+            a = (go >= lo && go <= hi) ? -INFINITY : INFINITY;
+            b = (go >= lo && go <= hi) ? INFINITY : -INFINITY;
+        } else {
+            // reciprocal: hardware estimate and two Newton steps (within an
+            // ulp or two of 1 / gd; gd is far from the subnormal range)
+            double inv = __builtin_amdgcn_rcp(gd);
+            inv = fma(inv, fma(-gd, inv, 1.0), inv);
+            inv = fma(inv, fma(-gd, inv, 1.0), inv);
+            const double t1 = (lo - go) * inv, t2 = (hi - go) * inv;
+            a = fmin(t1, t2);
+            b = fmax(t1, t2);
+        }
+        if (a > tn) {
+            tn = a;
+            ea = k;
+        }
+        tf = fmin(tf, b);
+    }
+    double te = tn;
+    if (!(te >= (double)r.tmin)) {
+        te = (double)r.tmin;
+        ea = 3;
+    }
+    t = (float)te;
+    axis = ea;
+    return te <= fmin(tf, (double)r.tmax);
 }
 
 // Bounding-sphere test of the paper's Sec. 4.1 (Eq. 4), made conservative
@@ -210,7 +275,9 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
 // size and table offsets are then launch-wide values (scalar registers)
 // rather than per-lane ones.
 // kInline: the frame table comes in the arguments (TraceArgsInline).
-template <bool kSorted, bool kSingle, bool kInline = false>
+// kCount: the counting build (TraceArgs::counts and trail), for tests and
+// measurement only.
+template <bool kSorted, bool kSingle, bool kInline = false, bool kCount = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 6 : 1, 8))) void trace_kernel(
     typename std::conditional<kInline, TraceArgsInline, TraceArgs>::type a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -280,10 +347,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     const FrameRec* src_frames = a.frames;
     const float4* src_sph = a.spheres;
     const uint32_t* src_cand = a.cand;
+    const double* xmaps = a.xmaps;   // read only at hits: stays in global memory
     if constexpr (kInline) {
         src_frames = reinterpret_cast<const FrameRec*>(a.inline_tab);
         src_sph = reinterpret_cast<const float4*>(a.inline_tab + a.inline_off_sph);
         src_cand = reinterpret_cast<const uint32_t*>(a.inline_tab + a.inline_off_cand);
+        xmaps = reinterpret_cast<const double*>(a.inline_tab + a.inline_off_x);
     }
     {
         const uint4* src = reinterpret_cast<const uint4*>(src_frames);
@@ -318,6 +387,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // per-lane state
     uint32_t mode = M_DONE;
     uint32_t ri = 0;           // ray index within its job (a launch holds at most 0xff000000 rays)
+    uint32_t gray = 0, c_nodes = 0, c_frames = 0, c_trail = 0;   // counting build only
     uint32_t job = 0;
     const uint64_t* nodes = kSingle ? a.job0.nodes : nullptr;
     uint32_t n_lds = kSingle ? min(a.job0.lds_nodes, fill_nodes) : 0u;
@@ -343,8 +413,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     uint32_t slot = 1, sbase = 0, top = 0;
     uint32_t lds_last = n_lds ? n_lds - 1u : 0u;  // the last cached node index (0 with no cache: reads stay in bounds)
     float tc0 = 0.f;
-    int eaxis = 3;
-    bool resume = false;
+    // what the next walk step does first: PEND_RESUME continue just past a
+    // transformed cell the walk came back from; PEND_ROOT_HIT the frame root
+    // is itself a solid leaf (recorded where every walk hit is)
+    uint32_t pend = 0;
     bool exhausted = !active;  // wave-uniform
 
     auto record_hit = [&](float t, uint32_t id, uint32_t f, int axis) {
@@ -364,13 +436,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         const FrameRec& F = lds_frames[f];
         if (F.info & FR_EMPTY) return false;
         float t0;
-        int ea;
-        if (!frame_setup(F, r, tl, fr, t0, ea)) return false;
-        if (F.info & FR_ROOT_LEAF) {
-            record_hit(t0, F.root, f, ea);
-            return false;
+        if (!frame_setup<true>(F, r, tl, fr, t0)) return false;
+        if constexpr (kCount) {
+            ++c_frames;
+            ++c_nodes;   // the frame's root record
         }
         cur_f = f;
+        if (F.info & FR_ROOT_LEAF) {
+            px = py = pz = 0u;
+            size = 1u << fr.K;
+            pend = PEND_ROOT_HIT;
+            return true;
+        }
         pmask = F.info & FR_MASK;
         pchild = F.child;
         sbase = 0;
@@ -384,8 +461,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         py = (fmaf((float)size, fr.iy, fr.by) <= t0) ? size : 0u;
         pz = (fmaf((float)size, fr.iz, fr.bz) <= t0) ? size : 0u;
         tc0 = t0;
-        eaxis = ea;
-        resume = false;
+        pend = 0;
         return true;
     };
 
@@ -403,8 +479,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             if (!sphere_may_hit(lds_sph[f], r, tlim)) return false;
             FrameRay cfr;
             float t0;
-            int ea;
-            return frame_setup(lds_frames[f], r, tlim, cfr, t0, ea);
+            // the walk's own entry test rounds differently: widened so that
+            // no frame a full trace would walk is ruled out here
+            return frame_setup<false>(lds_frames[f], r, tlim + fabsf(tlim) * 0x1p-18f, cfr, t0);
         };
         const JobRec& J = lds_jobs[job];
         if (!J.out_inst) return false;
@@ -458,6 +535,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             nz = row[2] * inv;
         }
         const JobRec& J = lds_jobs[job];
+        if constexpr (kCount) {
+            gst(a.counts, (uint64_t)gray, c_nodes);
+            gst(a.counts, n_rays + gray, c_frames);
+            atomicAdd(a.counts + 2 * n_rays + gray, 1u);
+        }
         gst(J.out_id, ri, best_id);
         if (J.out_inst) gst(J.out_inst, ri, best_inst);
         gst(J.out_t, ri, best_t);
@@ -521,6 +603,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 uint64_t gidx = n_rays;
                 if (rank < take && slot < n_tiles) gidx = ((slot * tstride) % n_tiles) * 64u + (j & 63u);
                 if (gidx < n_rays) {
+                    if constexpr (kCount) {
+                        gray = (uint32_t)gidx;
+                        c_nodes = c_frames = c_trail = 0;
+                    }
                     const float4* rays;
                     if constexpr (kSingle) {
                         ri = (uint32_t)(gidx - a.job0.ray_begin);
@@ -570,8 +656,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                                 if (sphere_may_hit(lds_sph[f], r, tl)) {
                                     FrameRay cfr;
                                     float t0;
-                                    int ea;
-                                    if (frame_setup(lds_frames[f], r, tl, cfr, t0, ea)) e = t0;
+                                    if (frame_setup<false>(lds_frames[f], r, tl, cfr, t0)) e = t0;
                                 }
                                 ent[c * 64] = e;
                             }
@@ -622,15 +707,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 pmask = stkm[slot * 64];
                 size = nsize;
                 tc0 = tc1;
-                eaxis = sx ? 0 : (sy ? 1 : 2);   // the lowest axis crossed
                 return EV_NONE;
             };
             uint32_t ev = EV_NONE;
             uint32_t hit_id = 0, xf = 0;
             float xf_tc1 = 0.f;
-            if (resume) {
+            const bool hit_root = pend == PEND_ROOT_HIT;
+            if (hit_root) {
+                pend = 0;
+                ev = EV_HIT;
+                hit_id = lds_frames[cur_f].root;
+            } else if (pend == PEND_RESUME) {
                 // continue just past a transformed cell the walk came back from
-                resume = false;
+                pend = 0;
                 const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
                 const float ey = fmaf((float)(py + size), fr.iy, fr.by);
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
@@ -660,6 +749,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     uint64_t wg = 0;
                     if (cidx >= n_lds) wg = gld(nodes, cidx);
                     const uint64_t w = (cidx < n_lds) ? wl : wg;
+                    if constexpr (kCount) {
+                        if (a.trail && c_trail < a.trail_cap)
+                            gst(a.trail, (uint64_t)c_trail * n_rays + gray, cidx | ((cidx < n_lds) ? 0x80000000u : 0u));
+                        ++c_trail;
+                        ++c_nodes;
+                    }
                     const uint32_t w0 = (uint32_t)w;
                     const uint32_t w1 = (uint32_t)(w >> 32);
                     const uint32_t cm = w0 & 0xFFu;
@@ -693,10 +788,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 ev = advance(ex, ey, ez, tc1);
             }
             if (ev == EV_HIT) {
-                // the first solid leaf front to back ends this top-level frame
-                record_hit(tc0, hit_id, cur_f, eaxis);
-                mode = M_SELECT;
-                nest = 0;
+                // the first solid leaf front to back ends this top-level frame;
+                // a leaf the ray passes by in FP64 is empty for this ray (the
+                // walk goes on past it; a frame root leaf ends the frame)
+                int ha;
+                float th;
+                if (exact_hit(xmaps + (size_t)kExactMapDoubles * cur_f, r, fr, px, py, pz, size, th, ha)) {
+                    record_hit(th, hit_id, cur_f, ha);
+                    mode = M_SELECT;
+                    nest = 0;
+                } else if (hit_root) {
+                    mode = M_SELECT;
+                    nest = 0;
+                } else {
+                    pend = PEND_RESUME;
+                }
             } else if (ev == EV_LIMIT) {
                 best_id = kStepLimitId;
                 finish();
@@ -704,12 +810,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 const FrameRec& C = lds_frames[xf];
                 FrameRay cfr;
                 float t0;
-                int ea;
-                if (frame_setup(C, r, fminf(tl, xf_tc1), cfr, t0, ea)) {
+                if (frame_setup<true>(C, r, fminf(tl, xf_tc1), cfr, t0)) {
+                    if constexpr (kCount) {
+                        ++c_frames;
+                        ++c_nodes;   // the frame's root record
+                    }
                     // save where the enclosing walk stands (its current slot
                     // keeps its node), then enter in place
                     fst[nest * 64] =
-                        make_uint4(cur_f | ((slot - sbase) << 11) | (sbase << 16) | ((uint32_t)eaxis << 23), px, py, pz);
+                        make_uint4(cur_f | ((slot - sbase) << 11) | (sbase << 16), px, py, pz);
                     ++nest;
                     sbase = slot;
                     cur_f = xf;
@@ -725,9 +834,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     py = (fmaf((float)size, fr.iy, fr.by) <= t0) ? size : 0u;
                     pz = (fmaf((float)size, fr.iz, fr.bz) <= t0) ? size : 0u;
                     tc0 = t0;
-                    eaxis = ea;
                 } else {
-                    resume = true;  // missed it: the cell is empty for this ray
+                    pend = PEND_RESUME;  // missed it: the cell is empty for this ray
                 }
             } else if (ev == EV_END) {
                 if (nest > 0) {
@@ -738,18 +846,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     const uint32_t lvl = (e.x >> 11) & 31u;
                     sbase = (e.x >> 16) & 127u;
                     slot = sbase + lvl;
-                    eaxis = (int)((e.x >> 23) & 3u);
                     px = e.y;
                     py = e.z;
                     pz = e.w;
                     float t0;
-                    int ea;
-                    frame_setup(lds_frames[cur_f], r, tl, fr, t0, ea);
+                    frame_setup<true>(lds_frames[cur_f], r, tl, fr, t0);
                     size = 1u << (fr.K - lvl);
                     top = sbase + fr.K;
                     pchild = stkc[slot * 64];
                     pmask = stkm[slot * 64];
-                    resume = true;
+                    pend = PEND_RESUME;
                 } else {
                     mode = M_SELECT;
                 }
@@ -767,8 +873,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             sbase = top = 0;
             cur_f = nest = 0;
             tc0 = 0.f;
-            eaxis = 3;
-            resume = false;
+            pend = 0;
             if (++steps > a.step_limit) {
                 best_id = kStepLimitId;
                 finish();
@@ -867,7 +972,10 @@ hipError_t prepare_trace(size_t max_lds) {
                              reinterpret_cast<const void*>(&trace_kernel<true, false>),
                              reinterpret_cast<const void*>(&trace_kernel<false, true>),
                              reinterpret_cast<const void*>(&trace_kernel<false, false>),
-                             reinterpret_cast<const void*>(&trace_kernel<true, true, true>)};
+                             reinterpret_cast<const void*>(&trace_kernel<true, true, true>),
+                             reinterpret_cast<const void*>(&trace_kernel<true, true, false, true>),
+                             reinterpret_cast<const void*>(&trace_kernel<false, true, false, true>),
+                             reinterpret_cast<const void*>(&trace_kernel<true, true, true, true>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
         if (e != hipSuccess) return e;
@@ -896,6 +1004,24 @@ hipError_t launch_trace(const TraceArgs& a, const LaunchCfg& c, hipStream_t stre
             hipLaunchKernelGGL((trace_kernel<false, true>), grid, block, c.lds_bytes, stream, a);
         else
             hipLaunchKernelGGL((trace_kernel<false, false>), grid, block, c.lds_bytes, stream, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_counted(const TraceArgs& a, const LaunchCfg& c, hipStream_t stream,
+                                const unsigned char* inline_tab, size_t inline_bytes) {
+    const dim3 grid(c.blocks), block(c.waves_per_block * 64);
+    if (!a.counts || a.jobs || a.hdr) return hipErrorInvalidValue;
+    if (inline_tab) {
+        if (!a.sort_cand || inline_bytes > kInlineTableBytes) return hipErrorInvalidValue;
+        TraceArgsInline ai{};
+        static_cast<TraceArgs&>(ai) = a;
+        std::memcpy(ai.inline_tab, inline_tab, inline_bytes);
+        hipLaunchKernelGGL((trace_kernel<true, true, true, true>), grid, block, c.lds_bytes, stream, ai);
+    } else if (a.sort_cand) {
+        hipLaunchKernelGGL((trace_kernel<true, true, false, true>), grid, block, c.lds_bytes, stream, a);
+    } else {
+        hipLaunchKernelGGL((trace_kernel<false, true, false, true>), grid, block, c.lds_bytes, stream, a);
     }
     return hipGetLastError();
 }

@@ -28,7 +28,8 @@ MAX_INLINE_NEST = 4
 EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "svo_validate", "svo_upload",
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
            "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
-           "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_shade", "svo_plan_create", "svo_plan_set_jobs", "svo_plan_launch", "svo_plan_destroy")
+           "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_shade", "svo_plan_create", "svo_plan_set_jobs",
+           "svo_plan_launch", "svo_plan_destroy", "svo_trace_rays_counted")
 
 
 class SvoError(RuntimeError):
@@ -121,6 +122,7 @@ def lib():
         "svo_trace_rays": (I, [P, U32, P, U64, P, P, P, P, P]),
         "svo_trace_batch": (I, [P, ctypes.POINTER(Job), U32, P]),
         "svo_trace_rays_reuse": (I, [P, U32, P, U64, P, P, P, P, P, P]),
+        "svo_trace_rays_counted": (I, [P, U32, P, U64, P, P, P, P, P, P, U32, P]),
         "svo_shade": (I, [P, U32, P, P, U32, U32, U32, U32, U32, U32, U32, P, P]),
         "svo_tune": (I, [P, U32, P, U64, P, ctypes.POINTER(Config)]),
         "svo_generate_primary_rays": (I, [P, ctypes.POINTER(Camera), P, P]),
@@ -394,6 +396,25 @@ class Context:
         out_t, and optionally out_inst, out_normal, fwd (host [n_slots, 12])."""
         arr, keep = _job_array(jobs)
         _check(lib().svo_trace_batch(self._ptr, arr, len(jobs), _stream_handle(stream)))
+
+    def trace_counted(self, scene: int, rays, trail_cap: int = 0, stream=None):
+        """svo_trace_rays_counted: (hits, counts [3, n] int32 tensor, trail
+        [trail_cap, n] int32 tensor or None)."""
+        import torch
+        if not rays.is_cuda or rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8:
+            raise ValueError("rays must be a float32 device tensor of shape [n, 8]")
+        rays = rays.contiguous()
+        n = rays.shape[0]
+        dev = rays.device
+        h = Hits(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+                 torch.empty(n, dtype=torch.float32, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev))
+        counts = torch.zeros((3, n), dtype=torch.int32, device=dev)
+        trail = torch.zeros((trail_cap, n), dtype=torch.int32, device=dev) if trail_cap else None
+        _check(lib().svo_trace_rays_counted(self._ptr, int(scene), rays.data_ptr(), n, h.id.data_ptr(),
+                                            h.inst.data_ptr(), h.t.data_ptr(), h.normal.data_ptr(), counts.data_ptr(),
+                                            trail.data_ptr() if trail is not None else None, int(trail_cap),
+                                            _stream_handle(stream)))
+        return h, counts, trail
 
     def plan(self, scenes, max_jobs: int = 64, max_frames: int = 512) -> "Plan":
         """A reusable (graph-capturable) batched launch for jobs on `scenes`."""

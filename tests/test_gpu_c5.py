@@ -1,9 +1,9 @@
 """Depth-12 ridged terrain (4096^3, ~1.5e8 nodes = 1.2 GB pool, 256 animated
 level-4 subtrees, candidates through the box hierarchy): full 3840x2160
 launches of primary rays and 2 AO rays per pixel, in the autotuned
-configuration the benchmark runs, checked against the oracle
-on sampled rays (every 997th ray plus one whole 64-ray tile) of two
-animation frames (needs the GPU)."""
+configuration the benchmark runs, checked against the oracle on every 17th
+pixel plus a 64x64-pixel block (about 492 k primary and 983 k AO rays) of two
+animation frames, at an id mismatch rate of at most 1e-4 (needs the GPU)."""
 import sys
 
 import numpy as np
@@ -31,24 +31,19 @@ def env():
     _say("nodes", sc.nodes.shape[0])
     ctx = svo.Context(0)
     h = ctx.upload_scene(sc)
-    rays_np, _ = sc.rays()
+    rays_np, pix = sc.rays()
     # the configuration the benchmark runs: tuned on frame 0's primary rays
     ctx.set_transforms(h, sc.xform(0))
     _say("tuned", ctx.tune(h, torch.from_numpy(rays_np).cuda()).as_dict())
-    yield torch, svo, ctx, sc, h, rays_np
+    yield torch, svo, ctx, sc, h, rays_np, pix
     ctx.free_scene(h)
     ctx.close()
 
 
-def _sample(n, W=3840):
-    every = np.arange(0, n, 997)
-    tile = np.arange(64) + 64 * 5000          # a whole 8x8-pixel tile ... 64 consecutive rays
-    return np.unique(np.concatenate([every, tile]))
-
-
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("frame", [0, 29])
 def test_primary_and_ao_sampled(env, frame):
-    torch, svo, ctx, sc, h, rays_np = env
+    torch, svo, ctx, sc, h, rays_np, pix = env
     fwd = sc.xform(frame)
     ctx.set_transforms(h, fwd)
     st = ctx.scene_stats(h)
@@ -59,14 +54,13 @@ def test_primary_and_ao_sampled(env, frame):
     ao = ctx.ao_rays(r, prim, k=2, seed=5, radius=64.0)
     out = ctx.trace(h, ao)
     torch.cuda.synchronize()
-    n = rays_np.shape[0]
-    idx = _sample(n)
+    idx = parity.survey_sample(pix, 3840, 2160)
     g = parity.to_numpy(prim)
     got = tuple(x[idx] for x in g)
     ref = oracle.trace_scene(sc, rays_np[idx], fwd=fwd, margin=True)
     stp = parity.compare(got, ref, ref.margin, rays_np[idx])
     _say("primary", stp, "slot hits", int((ref.inst != 0xFFFFFFFF).sum()))
-    parity.assert_parity(stp, 1e-3 if idx.shape[0] < 10000 else 1e-4)
+    parity.assert_parity(stp, 1e-4)
     assert (ref.id != 0xFFFFFFFF).mean() > 0.5
     # AO rays of the same sample's pixels (2 per pixel, consecutive)
     aidx = np.stack([2 * idx, 2 * idx + 1], 1).reshape(-1)
@@ -76,4 +70,4 @@ def test_primary_and_ao_sampled(env, frame):
     refa = oracle.trace_scene(sc, a, fwd=fwd, margin=True)
     sta = parity.compare(gota, refa, refa.margin, a)
     _say("ao", sta, "occluded", float((refa.id != 0xFFFFFFFF).mean()))
-    parity.assert_parity(sta, 1e-3)
+    parity.assert_parity(sta, 1e-4)

@@ -72,12 +72,14 @@ def test_ao_rays(env):
     parity.assert_parity(st, 1e-4)
 
 
+@pytest.mark.timeout(600)
 def test_full_resolution_in_the_benchmark_launch(env):
     """1920x1080 primary rays and 4 AO rays per pixel under the configuration
-    the autotuner picks (as the benchmark runs them): every 997th ray and one
-    whole 64-ray tile of each checked against the oracle one by one."""
+    the autotuner picks (as the benchmark runs them): every 17th pixel plus a
+    64x64-pixel block (about 126 k primary and 503 k AO rays) checked against
+    the oracle one by one, at an id mismatch rate of at most 1e-4."""
     torch, ctx, sc, h = env
-    rays, _ = sc.rays()
+    rays, pix = sc.rays()
     r = torch.from_numpy(rays).cuda()
     cfg = ctx.tune(h, r)
     _say("tuned", cfg.as_dict())
@@ -85,17 +87,16 @@ def test_full_resolution_in_the_benchmark_launch(env):
     ao = ctx.ao_rays(r, prim, k=4, seed=3, radius=64.0)
     out = ctx.trace(h, ao)
     torch.cuda.synchronize()
-    n = rays.shape[0]
-    idx = np.unique(np.concatenate([np.arange(0, n, 997), np.arange(64 * 3000, 64 * 3001)]))
+    idx = parity.survey_sample(pix, 1920, 1080)
     g = parity.to_numpy(prim)
     ref = oracle.trace_scene(sc, rays[idx], margin=True)
     st = parity.compare(tuple(x[idx] for x in g), ref, ref.margin, rays[idx])
     _say("primary 1080p sampled", st)
-    parity.assert_parity(st, 1e-3)
+    parity.assert_parity(st, 1e-4)
     aidx = (4 * idx[:, None] + np.arange(4)[None, :]).reshape(-1)
     a = ao[torch.from_numpy(aidx).cuda()].cpu().numpy()
     ga = parity.to_numpy(out)
     refa = oracle.trace_scene(sc, a, margin=True)
     sta = parity.compare(tuple(x[aidx] for x in ga), refa, refa.margin, a)
     _say("ao sampled", sta)
-    parity.assert_parity(sta, 1e-3)
+    parity.assert_parity(sta, 1e-4)
