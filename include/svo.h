@@ -265,6 +265,23 @@ typedef struct {
    the kernel arguments, with no copy. */
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
 
+/* svo_trace_batch without device allocation, for callers that cannot
+   allocate: code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc.  Same jobs, limits and results as svo_trace_batch,
+   but the work queue and the launch's tables live in one fixed scratch
+   array per device inside the library (264 KiB: an 8.25 KiB work queue,
+   then 256 KiB of tables), held until the process ends; the call allocates
+   no device or pinned memory.  The tables are packed into pinned staging
+   that svo_create set up and copied on `stream`; the call waits on the host
+   until the previous call's copy has read that staging.  Each call first
+   clears the queue with a small kernel on `stream`.  Every call on a device,
+   from any context, shares that device's scratch, which keeps the last
+   call's contents: calls that overlap on one device race (order them on one
+   stream).  Errors: as svo_trace_batch, and SVO_ERANGE (nothing enqueued)
+   when the batch's job, frame, candidate, sphere, exact-map and hierarchy
+   records exceed 256 KiB (about 1,400 frame records). */
+int svo_trace_batch_static(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
+
 /* Composite traced hits into an RGBA8 image (the colour field of the
    paper's hit buffer, Sec. 4.3; images like its Fig. 6).  prim_id: device,
    width * height * samples ids of primary rays in ray order (8x8 tiles when

@@ -331,6 +331,12 @@ struct svo_ctx {
     };
     BatchBuf batch[4];
     uint32_t next_batch = 0;
+    // svo_trace_batch_static: this device's scratch (its queue, then its
+    // table area), pinned staging for the table and the event after the
+    // staging's last copy; all set up in svo_create
+    unsigned char* d_static = nullptr;
+    unsigned char* h_static = nullptr;
+    hipEvent_t static_ev = nullptr;
     std::set<svo_plan*> plans;
 };
 
@@ -732,9 +738,25 @@ int svo_create(svo_ctx** out, int device_ordinal) {
     c->lds_per_cu = (size_t)std::max(lds_cu, lds);
     c->cfg = default_config();
     HIP_TRY(svo::prepare_trace(c->max_lds));
-    HIP_TRY(hipMalloc((void**)&c->d_queue, kMaxStreams * svo::kQueueWords * sizeof(uint32_t)));
-    HIP_TRY(hipMemset(c->d_queue, 0, kMaxStreams * svo::kQueueWords * sizeof(uint32_t)));
-    HIP_TRY(hipDeviceSynchronize());
+    auto undo = [&](int code, const char* what, hipError_t e) {
+        if (c->d_queue) (void)hipFree(c->d_queue);
+        if (c->h_static) (void)hipHostFree(c->h_static);
+        if (c->static_ev) (void)hipEventDestroy(c->static_ev);
+        return fail(code, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipMalloc((void**)&c->d_queue, kMaxStreams * svo::kQueueWords * sizeof(uint32_t));
+    if (e != hipSuccess) return undo(SVO_ENOMEM, "work queue allocation", e);
+    if ((e = hipMemset(c->d_queue, 0, kMaxStreams * svo::kQueueWords * sizeof(uint32_t))) != hipSuccess)
+        return undo(SVO_EDEVICE, "work queue clear", e);
+    // the allocation-free entry point's scratch: found once per device, its
+    // queue cleared here (its kernels leave the queue at zero on exit)
+    if ((e = svo::static_scratch(device_ordinal, &c->d_static)) != hipSuccess) return undo(SVO_EDEVICE, "scratch lookup", e);
+    if ((e = hipMemset(c->d_static, 0, svo::kStaticQueueBytes)) != hipSuccess) return undo(SVO_EDEVICE, "scratch clear", e);
+    if ((e = hipHostMalloc((void**)&c->h_static, svo::kStaticTableBytes, hipHostMallocDefault)) != hipSuccess)
+        return undo(SVO_ENOMEM, "pinned staging allocation", e);
+    if ((e = hipEventCreateWithFlags(&c->static_ev, hipEventDisableTiming)) != hipSuccess)
+        return undo(SVO_EDEVICE, "event creation", e);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return undo(SVO_EDEVICE, "set-up", e);
     *out = c.release();
     return SVO_OK;
 }
@@ -756,6 +778,8 @@ void svo_destroy(svo_ctx* ctx) {
         if (b.ev) (void)hipEventDestroy(b.ev);
     }
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
+    if (ctx->h_static) (void)hipHostFree(ctx->h_static);
+    if (ctx->static_ev) (void)hipEventDestroy(ctx->static_ev);
     delete ctx;
 }
 
@@ -1224,8 +1248,10 @@ int svo_trace_rays_reuse(svo_ctx* ctx, svo_scene scene, const float* rays, uint6
 
 namespace {
 
-// svo_trace_batch.
-int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
+// svo_trace_batch, and with use_static its allocation-free variant: the
+// work queue and the launch's tables in the device's scratch instead of a
+// per-stream queue and the ring of batch tables (allocated on first use).
+int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream, bool use_static) {
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     if (n_jobs && !jobs) return fail(SVO_EINVAL, "jobs is NULL");
     try {
@@ -1235,10 +1261,15 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
         if (P.jobs.empty()) return SVO_OK;
         if (P.frames > 2047) return fail(SVO_ERANGE, "a batch may hold at most 2047 frame records (has %u)", P.frames);
         hipStream_t st = (hipStream_t)stream;
-        uint32_t qslot;
-        rc = queue_slot(ctx, st, qslot);
-        if (rc) return rc;
-        uint32_t* queue = ctx->d_queue + svo::kQueueWords * qslot;
+        uint32_t* queue = nullptr;
+        if (use_static) {
+            queue = reinterpret_cast<uint32_t*>(ctx->d_static);
+        } else {
+            uint32_t qslot;
+            rc = queue_slot(ctx, st, qslot);
+            if (rc) return rc;
+            queue = ctx->d_queue + svo::kQueueWords * qslot;
+        }
         HIP_TRY(hipSetDevice(ctx->device));
 
         // configuration and node cache: the pool with the most rays in this batch
@@ -1290,7 +1321,39 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
             a.inline_off_sph = (uint32_t)sphere_offset(S.n_frames, S.n_slots);
             a.inline_off_x = (uint32_t)xmap_offset(S.n_frames, S.n_slots);
             const unsigned char* tab = Q.table.empty() ? S.h_stage[S.cur] : Q.table.data();
+            if (use_static) HIP_TRY(svo::launch_zero_words(queue, svo::kQueueWords, st));
             return launch(ctx, cfg, a, st, tab, bvh_offset(S.n_frames, S.n_slots));
+        }
+
+        if (use_static) {
+            if (bytes > svo::kStaticTableBytes)
+                return fail(SVO_ERANGE, "the batch's tables take %zu bytes; the allocation-free launch holds %zu", bytes,
+                            svo::kStaticTableBytes);
+            // the staging may still feed the previous call's copy
+            HIP_TRY(hipEventSynchronize(ctx->static_ev));
+            unsigned char* H = ctx->h_static;
+            unsigned char* D = ctx->d_static + svo::kStaticQueueBytes;
+            write_tables(P, reinterpret_cast<svo::JobRec*>(H), reinterpret_cast<svo::FrameRec*>(H + jb),
+                         reinterpret_cast<uint32_t*>(H + jb + fb), reinterpret_cast<float*>(H + sb),
+                         reinterpret_cast<double*>(H + xb), reinterpret_cast<svo::BvhNode*>(H + bb), a.lds_nodes);
+            a.jobs = reinterpret_cast<const svo::JobRec*>(D);
+            if (P.jobs.size() == 1) {
+                a.job0 = *reinterpret_cast<const svo::JobRec*>(H);
+                a.jobs = nullptr;
+            }
+            a.frames = reinterpret_cast<const svo::FrameRec*>(D + jb);
+            a.cand = reinterpret_cast<const uint32_t*>(D + jb + fb);
+            a.spheres = reinterpret_cast<const float4*>(D + sb);
+            a.xmaps = reinterpret_cast<const double*>(D + xb);
+            a.bvh = reinterpret_cast<const svo::BvhNode*>(D + bb);
+            HIP_TRY(svo::launch_zero_words(queue, svo::kQueueWords, st));
+            HIP_TRY(hipMemcpyAsync(D, H, bytes, hipMemcpyHostToDevice, st));
+            rc = launch(ctx, cfg, a, st);
+            // recorded even when the launch failed: the copy still reads H
+            const hipError_t e = hipEventRecord(ctx->static_ev, st);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(SVO_EDEVICE, "event record failed: %s", hipGetErrorString(e));
+            return SVO_OK;
         }
 
         auto& B = ctx->batch[ctx->next_batch];
@@ -1340,7 +1403,11 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
 extern "C" {
 
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
-    return trace_batch(ctx, jobs, n_jobs, stream);
+    return trace_batch(ctx, jobs, n_jobs, stream, false);
+}
+
+int svo_trace_batch_static(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream) {
+    return trace_batch(ctx, jobs, n_jobs, stream, true);
 }
 
 // ------------------------------------------------------------------ plans

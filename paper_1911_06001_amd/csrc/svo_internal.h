@@ -85,6 +85,13 @@ constexpr uint32_t kQueueDry = kQueueParts * kQueueStride;         // 2 words: b
 constexpr uint32_t kQueueFinished = kQueueDry + kQueueStride;      // finished work-groups
 constexpr uint32_t kQueueWords = kQueueFinished + kQueueStride;
 
+// Scratch of the allocation-free batched entry point: one work queue, then
+// a table area for the launch's job, frame, candidate, sphere, exact-map and
+// hierarchy records.  One copy per device, in the library's code object.
+constexpr size_t kStaticQueueBytes = ((size_t)kQueueWords * 4 + 255) & ~(size_t)255;
+constexpr size_t kStaticTableBytes = (size_t)256 << 10;
+constexpr size_t kStaticScratchBytes = kStaticQueueBytes + kStaticTableBytes;
+
 // Launch-wide counts of a plan launch, read by the kernel from the head of
 // the plan's device table: a captured launch keeps its arguments across
 // replays, so whatever changes between replays lives in device memory.
@@ -209,6 +216,13 @@ struct ShadeArgs {
 };
 
 hipError_t launch_shade(const ShadeArgs& a, hipStream_t stream);
+
+// Device address of this device's scratch (kStaticScratchBytes, 256-byte
+// aligned), looked up once per device; the device must be current.
+hipError_t static_scratch(int device, unsigned char** out);
+// Zero n 32-bit words on `stream` with a small kernel (no memset node, so
+// the clear may be captured into a graph).
+hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t stream);
 
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block);
 // Allow the trace kernel up to max_lds bytes of dynamic LDS on the current

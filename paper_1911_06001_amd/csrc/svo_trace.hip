@@ -38,6 +38,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "svo_internal.h"
@@ -965,6 +966,38 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             atomicExch(fin, 0u);
         }
     }
+}
+
+// The allocation-free entry point's scratch (see static_scratch).  In host
+// code this name is not a device address: host code reaches the array only
+// through the pointer static_scratch returns.
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(int device, unsigned char** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned char* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices || !out) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<unsigned char*>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t* p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
 }
 
 hipError_t prepare_trace(size_t max_lds) {

@@ -29,7 +29,7 @@ EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "sv
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
            "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
            "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_shade", "svo_plan_create", "svo_plan_set_jobs",
-           "svo_plan_launch", "svo_plan_destroy", "svo_trace_rays_counted")
+           "svo_plan_launch", "svo_plan_destroy", "svo_trace_batch_static", "svo_trace_rays_counted")
 
 
 class SvoError(RuntimeError):
@@ -121,6 +121,7 @@ def lib():
         "svo_set_transforms": (I, [P, U32, U32, U32, P, P]),
         "svo_trace_rays": (I, [P, U32, P, U64, P, P, P, P, P]),
         "svo_trace_batch": (I, [P, ctypes.POINTER(Job), U32, P]),
+        "svo_trace_batch_static": (I, [P, ctypes.POINTER(Job), U32, P]),
         "svo_trace_rays_reuse": (I, [P, U32, P, U64, P, P, P, P, P, P]),
         "svo_trace_rays_counted": (I, [P, U32, P, U64, P, P, P, P, P, P, U32, P]),
         "svo_shade": (I, [P, U32, P, P, U32, U32, U32, U32, U32, U32, U32, P, P]),
@@ -415,6 +416,12 @@ class Context:
                                             trail.data_ptr() if trail is not None else None, int(trail_cap),
                                             _stream_handle(stream)))
         return h, counts, trail
+
+    def trace_batch_static(self, jobs, stream=None):
+        """As trace_batch, through the allocation-free entry point (the
+        library's per-device scratch; calls on one device must not overlap)."""
+        arr, keep = _job_array(jobs)
+        _check(lib().svo_trace_batch_static(self._ptr, arr, len(jobs), _stream_handle(stream)))
 
     def plan(self, scenes, max_jobs: int = 64, max_frames: int = 512) -> "Plan":
         """A reusable (graph-capturable) batched launch for jobs on `scenes`."""
