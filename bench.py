@@ -158,11 +158,12 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def instances_throughput(ctx, steps):
+def instances_throughput(ctx, steps, knobs=None):
     """Instanced scene (64 DAG-shared instances of 4 SVOs in a 4096^3 world):
     1080p primary rays, then 4 cosine-weighted AO rays per pixel from the
     primary hits (incoherent).  Mrays/s of each trace, kernel time from HIP
-    events on the launch stream."""
+    events on the launch stream.  With ``knobs`` the kernel runs that
+    configuration instead of the autotuner's."""
     import torch
     from svogen import scenes
     t0 = time.perf_counter()
@@ -175,7 +176,10 @@ def instances_throughput(ctx, steps):
     n = rays.shape[0]
     prim = ctx.trace(h, rays)
     ao = ctx.ao_rays(rays, prim, k=4, seed=3, radius=64.0)
-    ctx.tune(h, rays)
+    if knobs:
+        ctx.set_config(**knobs)
+    else:
+        ctx.tune(h, rays)
     out_ao = ctx.trace(h, ao)
     stream = torch.cuda.current_stream()
     res = {}
@@ -306,7 +310,7 @@ def serve_c5(ctx, c5_scene, c5_handle, n_requests, load):
     log("serving depth-12 + instances at %.1f load: batched p50 %.1f p99 %.1f ms, single p50 %.1f p99 %.1f ms, "
         "peak admitted %.1f GiB" % (load, b["p50_ms"], b["p99_ms"], s1["p50_ms"], s1["p99_ms"], max_used / 2**30))
     return {"requests": n_requests, "offered_load": load, "saturation_rps": round(rate, 2), "hbm_budget_bytes": budget,
-            "peak_admitted_bytes": int(max_used),
+            "resident_scene_bytes": int(srv.resident_bytes), "peak_admitted_bytes": int(max_used),
             "mix": "terrain4096 3840x2160 + 2 AO rays/pixel and instances4096 1920x1080 + 4 AO rays/pixel, "
                    "Poisson arrivals",
             "batched": b, "single": s1}
@@ -351,7 +355,8 @@ def serve_latency(ctx, terrain, terrain_handle, n_requests, loads, warm=100):
     srv_g.close()
     ctx.free_scene(hs)
     return {"requests": n_requests, "warmup_requests": warm, "saturation_rps": round(rate, 1),
-            "hbm_budget_bytes": budget, "policy": srv.policy, "max_rays_per_step": srv.max_rays,
+            "hbm_budget_bytes": budget, "resident_scene_bytes": int(srv.resident_bytes), "policy": srv.policy,
+            "max_rays_per_step": srv.max_rays,
             "solo_rays_per_step": srv.solo_rays, "step_streams": srv.inflight_steps,
             "mix": "sphere64 + terrain1024 scenes, 256^2/720p/1080p/2048x1152, 1-5 rays per pixel, Poisson arrivals",
             "points": points}
@@ -381,6 +386,9 @@ def main():
     ap.add_argument("--no-hit-buffer", action="store_true", help="skip the hit-buffer (frame-to-frame reuse) run")
     ap.add_argument("--c5-only", action="store_true",
                     help="run only the depth-12 terrain leg (for profiling) and print its JSON")
+    ap.add_argument("--instances-only", action="store_true",
+                    help="run only the instanced-scene leg (for profiling) and print its JSON")
+    ap.add_argument("--no-camera", action="store_true", help="skip the camera-ray (in-kernel generation) run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -423,6 +431,12 @@ def main():
         ctx.free_scene(h5)
         ctx.close()
         print(json.dumps({"c5_only": res}), flush=True)
+        return
+    if args.instances_only:
+        ctx = svo.Context(0)
+        res = instances_throughput(ctx, args.steps, knobs=knobs or None)
+        ctx.close()
+        print(json.dumps({"instances_only": res}), flush=True)
         return
 
     t0 = time.perf_counter()
@@ -496,6 +510,35 @@ def main():
     log("animated: %.3f ms/step wall, kernel mean %.3f ms" % (wall_a / K * 1e3, float(np.mean(kms_a))))
     wall_s, kms_s = timed(step_static, K)
     log("static: %.3f ms/step wall, kernel mean %.3f ms" % (wall_s / K * 1e3, float(np.mean(kms_s))))
+
+    # The same frames with the primary rays made inside the trace kernel
+    # from the camera (svo_trace_camera: no ray buffer read).  Reported
+    # beside the headline, which reads its rays.
+    camera_run = None
+    c = sc.camera
+    cam = svo.make_camera(c["eye"], c["target"], c["up"], c["fov"], args.width, args.height)
+    cam_hits = svo.Hits(out_id, out_inst, out_t, out_n)
+    n_cam_steps = 0 if args.no_camera else K
+    if n_cam_steps:
+        for k in range(3):
+            ctx.set_transforms(anim, xf[frame_of(k)], stream=stream)
+            ctx.trace_camera(anim, cam, out=cam_hits, stream=stream)
+        cevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for k in range(K):
+            ctx.set_transforms(anim, xf[frame_of(k)], stream=stream)
+            cevs[k][0].record(stream)
+            ctx.trace_camera(anim, cam, out=cam_hits, stream=stream)
+            cevs[k][1].record(stream)
+        torch.cuda.synchronize()
+        cwall = time.perf_counter() - w0
+        ckms = float(np.mean([x.elapsed_time(y) for x, y in cevs]))
+        camera_run = {"value": round(n * K / cwall / 1e6, 3), "unit": "Mrays/s",
+                      "ms_per_step": round(cwall / K * 1e3, 4), "kernel_ms": round(ckms, 4),
+                      "note": "same frames; rays made in the trace kernel from a 96-byte camera record "
+                              "(svo_trace_camera)"}
+        log("camera rays: %.3f ms/step wall, kernel %.3f ms" % (cwall / K * 1e3, ckms))
 
     # Two frames in flight: frame k traces on stream k mod 2 into its own
     # outputs, so the next frame's launch fills the CUs that this one frees
@@ -636,6 +679,7 @@ def main():
         "animated_over_static_time": round(wall_a / wall_s, 4),
         "animated_over_static_kernel_time": round(float(np.mean(kms_a)) / float(np.mean(kms_s)), 4),
         "two_frames_in_flight": pipe,
+        "camera_rays": camera_run,
         "hit_buffer": hb,
         "roofline": roof,
         "ceilings": ceilings,

@@ -239,18 +239,48 @@ int svo_trace_rays_counted(svo_ctx* ctx, svo_scene scene, const float* rays, uin
 int svo_trace_rays_reuse(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                          uint32_t* out_inst, float* out_t, float* out_normal, uint64_t* retraced, void* stream);
 
+/* Pinhole camera: the primary rays of svo_generate_primary_rays, and of a
+   camera trace (svo_trace_camera, svo_job.camera), which makes the same rays
+   inside the trace kernel instead of reading them.  forward, right and up are
+   unit vectors (right = forward x up); pixel (i, j), j counted from the top
+   row, sample s has direction normalize(forward + sx right + sy up) with
+   sx = ((i + fx) / width * 2 - 1) tan_half_fov * width / height and
+   sy = (1 - (j + fy) / height * 2) tan_half_fov, where (fx, fy) = (1/2, 1/2)
+   unless jitter is set, in which case they are hashed from (seed, pixel,
+   sample) into [0, 1).  Every ray has origin eye, tmin 0 and tmax +inf.
+   Ray order: tiled -- 8x8 pixel tiles, tile rows top to bottom, tiles left
+   to right, pixels row-major inside a tile, partial edge tiles holding only
+   in-image pixels; otherwise row-major pixels.  The samples of one pixel
+   are consecutive.  One pixel sample per ray, the paper's per-pixel form
+   (Fig. 5). */
+typedef struct {
+    float eye[3];
+    float forward[3];
+    float right[3];
+    float up[3];
+    float tan_half_fov;
+    uint32_t width, height;
+    uint32_t samples;         /* rays per pixel, >= 1 */
+    uint32_t seed;
+    uint32_t jitter;          /* 0: pixel centres */
+    uint32_t tiled;           /* 1: 8x8 pixel tiles (see below), 0: rows */
+    uint32_t reserved;
+} svo_camera;
+
 /* One job of a batched launch: rays traced against one scene under one set
    of transforms. */
 typedef struct {
     svo_scene scene;
     const float* fwd_3x4;     /* host, n_slots * 12 floats (every slot of the scene, parent-relative,
                                  as in svo_set_transforms), or NULL for the scene's current transforms */
-    const float* rays;        /* device, n * 8 floats, 16-byte aligned */
-    uint64_t n;
+    const float* rays;        /* device, n * 8 floats, 16-byte aligned; NULL with a camera */
+    uint64_t n;               /* rays; with a camera width * height * samples */
     uint32_t* out_id;         /* device outputs, as in svo_trace_rays */
     uint32_t* out_inst;       /* nullable */
     float* out_t;
     float* out_normal;        /* nullable */
+    const svo_camera* camera; /* host, nullable: the job's rays are made in the trace kernel from this
+                                 camera (read when the call packs the job), in the camera's ray order */
 } svo_job;
 
 /* Trace several jobs -- rays of many requests, scenes and animation frames
@@ -264,6 +294,18 @@ typedef struct {
    single job of a scene of at most 10 slots instead takes its frame table in
    the kernel arguments, with no copy. */
 int svo_trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream);
+
+/* Trace the primary rays of a camera (width * height * samples rays, in the
+   camera's ray order) without a ray buffer: the trace kernel makes each ray
+   from the camera where svo_trace_rays would read it (Eq. 1; Fig. 5, one
+   pixel sample per ray); results are identical to svo_generate_primary_rays
+   followed by svo_trace_rays.  cam: host, read during the call.  Outputs as
+   in svo_trace_rays, width * height * samples entries.  Errors: as
+   svo_trace_rays; SVO_EINVAL for a bad camera (zero size or samples, a
+   field of view that is not finite and positive), SVO_ERANGE for a side
+   above 2^20 pixels or more than 0xff000000 rays. */
+int svo_trace_camera(svo_ctx* ctx, svo_scene scene, const svo_camera* cam, uint32_t* out_id, uint32_t* out_inst,
+                     float* out_t, float* out_normal, void* stream);
 
 /* svo_trace_batch without device allocation, for callers that cannot
    allocate: code under HIP graph capture, tight serving loops, harnesses
@@ -377,34 +419,11 @@ int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
    outputs and synchronises `stream`; not for use inside a timed loop. */
 int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n, void* stream, svo_config* best);
 
-/* Pinhole camera for svo_generate_primary_rays.  forward, right and up are
-   unit vectors (right = forward x up); pixel (i, j), j counted from the top
-   row, sample s has direction normalize(forward + sx right + sy up) with
-   sx = ((i + fx) / width * 2 - 1) tan_half_fov * width / height and
-   sy = (1 - (j + fy) / height * 2) tan_half_fov, where (fx, fy) = (1/2, 1/2)
-   unless jitter is set, in which case they are hashed from (seed, pixel,
-   sample) into [0, 1). */
-typedef struct {
-    float eye[3];
-    float forward[3];
-    float right[3];
-    float up[3];
-    float tan_half_fov;
-    uint32_t width, height;
-    uint32_t samples;         /* rays per pixel, >= 1 */
-    uint32_t seed;
-    uint32_t jitter;          /* 0: pixel centres */
-    uint32_t tiled;           /* 1: 8x8 pixel tiles (see below), 0: rows */
-    uint32_t reserved;
-} svo_camera;
 
 /* Write width * height * samples primary rays (8 floats each, tmin = 0,
-   tmax = +inf) to out_rays (device, 16-byte aligned) on `stream`.  Order:
-   tiled -- 8x8 pixel tiles, tile rows top to bottom, tiles left to right,
-   pixels row-major inside a tile, partial edge tiles holding only in-image
-   pixels; otherwise row-major pixels.  The samples of one pixel are
-   consecutive.  SVO_ERANGE for a side above 2^20 pixels or more than
-   0xff000000 rays. */
+   tmax = +inf) to out_rays (device, 16-byte aligned) on `stream`, in the
+   camera's ray order (svo_camera).  SVO_ERANGE for a side above 2^20
+   pixels or more than 0xff000000 rays. */
 int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream);
 
 /* Ambient-occlusion rays from primary hits: for each of the n primary rays

@@ -348,7 +348,7 @@ struct svo_plan {
     svo::TraceArgs args{};
     svo::LaunchCfg launch_cfg{};
     uint32_t max_jobs = 0, max_frames = 0, max_cand = 0, stack_cap = 1, nest_cap = 0, max_bvh = 0, bvh_depth_cap = 0;
-    size_t off_jobs = 0, off_frames = 0, off_cand = 0, off_sph = 0, off_x = 0, off_bvh = 0, bytes = 0;
+    size_t off_jobs = 0, off_frames = 0, off_cand = 0, off_sph = 0, off_x = 0, off_bvh = 0, off_cams = 0, bytes = 0;
     unsigned char* dev = nullptr;
     unsigned char* host = nullptr;
     uint32_t* d_queue = nullptr;
@@ -1034,6 +1034,35 @@ void fill_common(const svo_config& c, svo::TraceArgs& a) {
     a.step_limit = c.step_limit;
 }
 
+// Validate a camera and fill the device record (svo_camera.h).
+int camera_args(const svo_camera* cam, svo::CameraArgs& c) {
+    if (!cam) return fail(SVO_EINVAL, "camera is NULL");
+    if (cam->width == 0 || cam->height == 0 || cam->samples == 0) return fail(SVO_EINVAL, "empty image");
+    if (cam->width > kMaxImageSide || cam->height > kMaxImageSide)
+        return fail(SVO_ERANGE, "image sides must be at most %u", kMaxImageSide);
+    if ((uint64_t)cam->width * cam->height * cam->samples > 0xFF000000ull) return fail(SVO_ERANGE, "too many rays");
+    if (!(cam->tan_half_fov > 0.f) || !std::isfinite(cam->tan_half_fov)) return fail(SVO_EINVAL, "bad field of view");
+    c = svo::CameraArgs{};
+    for (int a = 0; a < 3; ++a) {
+        c.eye[a] = cam->eye[a];
+        c.fwd[a] = cam->forward[a];
+        c.right[a] = cam->right[a];
+        c.up[a] = cam->up[a];
+    }
+    c.tan_half_fov = cam->tan_half_fov;
+    c.aspect = (float)cam->width / (float)cam->height;
+    c.width = cam->width;
+    c.height = cam->height;
+    c.samples = cam->samples;
+    c.seed = cam->seed;
+    c.jitter = cam->jitter ? 1u : 0u;
+    c.tiled = cam->tiled ? 1u : 0u;
+    c.full_tiles = (c.tiled && c.samples == 1 && c.width % 8 == 0 && c.height % 8 == 0) ? 1u : 0u;
+    c.tiles_x = (c.width + 7) / 8;
+    c.inv_tiles_x = 1.0 / (double)c.tiles_x;
+    return SVO_OK;
+}
+
 // Validated jobs of one launch, with their frame and candidate placement.
 struct PackedJob {
     Scene* S;
@@ -1041,6 +1070,8 @@ struct PackedJob {
     uint32_t frame_base, cand_base, bvh_base;
     std::vector<unsigned char> table;   // job-specific transforms (else the scene's current table)
     TableInfo T;
+    bool has_cam = false;               // rays made from `cam` in the kernel
+    svo::CameraArgs cam{};
 };
 
 struct Packing {
@@ -1061,10 +1092,20 @@ int pack_jobs(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, const std::set
         if (!S) return fail(SVO_EINVAL, "job %u: unknown scene %u", i, J.scene);
         if (allowed && !allowed->count(J.scene)) return fail(SVO_EINVAL, "job %u: scene %u is not one of the plan's", i, J.scene);
         if (J.n == 0) continue;
-        if (!J.rays || !J.out_id || !J.out_t) return fail(SVO_EINVAL, "job %u: rays, out_id and out_t are required", i);
-        if (((uintptr_t)J.rays) & 15u) return fail(SVO_EINVAL, "job %u: rays must be 16-byte aligned", i);
+        if (!J.out_id || !J.out_t) return fail(SVO_EINVAL, "job %u: out_id and out_t are required", i);
+        svo::CameraArgs cam{};
+        if (J.camera) {
+            if (J.rays) return fail(SVO_EINVAL, "job %u: a camera job takes no ray buffer", i);
+            const int rc = camera_args(J.camera, cam);
+            if (rc) return rc;
+            if (J.n != (uint64_t)cam.width * cam.height * cam.samples)
+                return fail(SVO_EINVAL, "job %u: n must be width * height * samples of its camera", i);
+        } else {
+            if (!J.rays) return fail(SVO_EINVAL, "job %u: rays are required", i);
+            if (((uintptr_t)J.rays) & 15u) return fail(SVO_EINVAL, "job %u: rays must be 16-byte aligned", i);
+        }
         if (P.jobs.size() >= svo::kMaxJobs) return fail(SVO_ERANGE, "at most %u non-empty jobs per launch", svo::kMaxJobs);
-        PackedJob Q{S, &J, P.frames, P.cands, P.bvh, {}, TableInfo()};
+        PackedJob Q{S, &J, P.frames, P.cands, P.bvh, {}, TableInfo(), J.camera != nullptr, cam};
         if (J.fwd_3x4) {
             std::vector<Aff> fwd(S->n_slots);
             for (uint32_t s = 0; s < S->n_slots; ++s) {
@@ -1111,8 +1152,10 @@ int pack_jobs(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, const std::set
 // spheres, exact maps and hierarchy nodes (skipped when br is null: launches
 // that take every candidate through the sorted path) of a packing into host
 // memory; the jobs of the cached pool get `cache_nodes` LDS nodes.
+// Camera jobs get their camera at cams[i] (host), which the launch reads at
+// dev_cams + i.
 void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t* cr, float* sr, double* xr,
-                  svo::BvhNode* br, uint32_t cache_nodes) {
+                  svo::BvhNode* br, uint32_t cache_nodes, svo::CameraArgs* cams, const svo::CameraArgs* dev_cams) {
     uint64_t begin = 0;
     for (size_t i = 0; i < P.jobs.size(); ++i) {
         const PackedJob& Q = P.jobs[i];
@@ -1129,7 +1172,9 @@ void write_tables(const Packing& P, svo::JobRec* jr, svo::FrameRec* fr, uint32_t
         const svo_job& J = *Q.j;
         jr[i] = svo::JobRec{S.d_nodes, reinterpret_cast<const float4*>(J.rays), J.out_id, J.out_inst, J.out_t,
                             J.out_normal, begin, Q.frame_base, Q.cand_base, Q.T.n_cand,
-                            S.d_nodes == P.cache_src ? cache_nodes : 0u, Q.bvh_base, Q.T.n_inline};
+                            S.d_nodes == P.cache_src ? cache_nodes : 0u, Q.bvh_base, Q.T.n_inline,
+                            Q.has_cam ? dev_cams + i : nullptr, 0};
+        if (Q.has_cam) cams[i] = Q.cam;
         begin += J.n;
     }
 }
@@ -1160,12 +1205,13 @@ namespace {
 
 int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id, uint32_t* out_inst,
                float* out_t, float* out_normal, void* stream, bool reuse, unsigned long long* retraced,
-               uint32_t* counts = nullptr, uint32_t* trail = nullptr, uint32_t trail_cap = 0) {
+               uint32_t* counts = nullptr, uint32_t* trail = nullptr, uint32_t trail_cap = 0,
+               const svo::CameraArgs* cam = nullptr) {
     if (!ctx) return fail(SVO_EINVAL, "ctx is NULL");
     Scene* S = find_scene(ctx, scene);
     if (!S) return fail(SVO_EINVAL, "unknown scene %u", scene);
     if (n == 0) return SVO_OK;
-    if (!rays || !out_id || !out_t) return fail(SVO_EINVAL, "rays, out_id and out_t are required");
+    if ((!rays && !cam) || !out_id || !out_t) return fail(SVO_EINVAL, "rays, out_id and out_t are required");
     if (((uintptr_t)rays) & 15u) return fail(SVO_EINVAL, "rays must be 16-byte aligned");
     if (n > 0xFF000000ull) return fail(SVO_ERANGE, "at most 0xff000000 rays per call");
     hipStream_t st = (hipStream_t)stream;
@@ -1215,6 +1261,10 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     a.counts = counts;
     a.trail = trail;
     a.trail_cap = trail ? trail_cap : 0u;
+    if (cam) {
+        a.has_cam0 = 1;
+        a.cam0 = *cam;
+    }
     return launch(ctx, cfg, a, st, tab, tab_bytes);
 }
 
@@ -1225,6 +1275,15 @@ extern "C" {
 int svo_trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
                    uint32_t* out_inst, float* out_t, float* out_normal, void* stream) {
     return trace_rays(ctx, scene, rays, n, out_id, out_inst, out_t, out_normal, stream, false, nullptr);
+}
+
+int svo_trace_camera(svo_ctx* ctx, svo_scene scene, const svo_camera* cam, uint32_t* out_id, uint32_t* out_inst,
+                     float* out_t, float* out_normal, void* stream) {
+    svo::CameraArgs c;
+    const int rc = camera_args(cam, c);
+    if (rc) return rc;
+    return trace_rays(ctx, scene, nullptr, (uint64_t)c.width * c.height * c.samples, out_id, out_inst, out_t, out_normal,
+                      stream, false, nullptr, nullptr, nullptr, 0, &c);
 }
 
 int svo_trace_rays_counted(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uint32_t* out_id,
@@ -1282,13 +1341,14 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
             }
         svo_config cfg = *pcfg;
 
-        // pack [jobs][frames][candidates][spheres][exact maps][hierarchy nodes]
+        // pack [jobs][frames][candidates][spheres][exact maps][hierarchy nodes][cameras]
         const size_t jb = P.jobs.size() * sizeof(svo::JobRec);
         const size_t fb = (size_t)P.frames * sizeof(svo::FrameRec);
         const size_t sb = (jb + fb + (size_t)P.cands * sizeof(uint32_t) + 15) & ~(size_t)15;
         const size_t xb = sb + (size_t)P.frames * 16;
         const size_t bb = xb + (size_t)P.frames * kXmapBytes;
-        const size_t bytes = bb + (size_t)P.bvh * sizeof(svo::BvhNode);
+        const size_t cb = bb + (size_t)P.bvh * sizeof(svo::BvhNode);
+        const size_t bytes = cb + P.jobs.size() * sizeof(svo::CameraArgs);
         svo::TraceArgs a{};
         a.n_bvh_total = P.max_cand > svo::kMaxSortedCand ? P.bvh : 0u;
         a.bvh_depth = P.bvh_depth;
@@ -1304,6 +1364,11 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
         a.stack_levels = P.stack_levels;
         a.nest_levels = P.nest_levels;
         fill_common(cfg, a);
+        if (P.jobs.size() == 1 && P.jobs[0].has_cam) {
+            // one job: its camera travels in the arguments
+            a.has_cam0 = 1;
+            a.cam0 = P.jobs[0].cam;
+        }
         // size LDS now: a smaller node cache changes the jobs' lds_nodes
         const size_t lds = fit_lds(ctx, a, cfg.waves_per_block);
         if (lds > ctx->max_lds) return fail(SVO_ERANGE, "batch needs %zu bytes of LDS per work-group", lds);
@@ -1335,7 +1400,8 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
             unsigned char* D = ctx->d_static + svo::kStaticQueueBytes;
             write_tables(P, reinterpret_cast<svo::JobRec*>(H), reinterpret_cast<svo::FrameRec*>(H + jb),
                          reinterpret_cast<uint32_t*>(H + jb + fb), reinterpret_cast<float*>(H + sb),
-                         reinterpret_cast<double*>(H + xb), reinterpret_cast<svo::BvhNode*>(H + bb), a.lds_nodes);
+                         reinterpret_cast<double*>(H + xb), reinterpret_cast<svo::BvhNode*>(H + bb), a.lds_nodes,
+                         reinterpret_cast<svo::CameraArgs*>(H + cb), reinterpret_cast<const svo::CameraArgs*>(D + cb));
             a.jobs = reinterpret_cast<const svo::JobRec*>(D);
             if (P.jobs.size() == 1) {
                 a.job0 = *reinterpret_cast<const svo::JobRec*>(H);
@@ -1373,7 +1439,8 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
         if (!B.ev) HIP_TRY(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
         write_tables(P, reinterpret_cast<svo::JobRec*>(B.host), reinterpret_cast<svo::FrameRec*>(B.host + jb),
                      reinterpret_cast<uint32_t*>(B.host + jb + fb), reinterpret_cast<float*>(B.host + sb),
-                     reinterpret_cast<double*>(B.host + xb), reinterpret_cast<svo::BvhNode*>(B.host + bb), a.lds_nodes);
+                     reinterpret_cast<double*>(B.host + xb), reinterpret_cast<svo::BvhNode*>(B.host + bb), a.lds_nodes,
+                     reinterpret_cast<svo::CameraArgs*>(B.host + cb), reinterpret_cast<const svo::CameraArgs*>(B.dev + cb));
         a.jobs = reinterpret_cast<const svo::JobRec*>(B.dev);
         if (P.jobs.size() == 1) {
             // one job: passed in the arguments, which selects the single-job
@@ -1440,7 +1507,7 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         pl->max_jobs = limits->max_jobs;
         pl->max_frames = limits->max_frames;
         pl->max_cand = std::min(max_slots, limits->max_frames);
-        // table layout: [header][jobs][frames][candidates][spheres][exact maps][hierarchy], capacities
+        // table layout: [header][jobs][frames][candidates][spheres][exact maps][hierarchy][cameras], capacities
         pl->off_jobs = sizeof(svo::LaunchHdr);
         pl->off_frames = pl->off_jobs + (size_t)pl->max_jobs * sizeof(svo::JobRec);
         pl->off_cand = pl->off_frames + (size_t)pl->max_frames * sizeof(svo::FrameRec);
@@ -1449,7 +1516,8 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         pl->off_bvh = pl->off_x + (size_t)pl->max_frames * kXmapBytes;
         pl->max_bvh = pl->max_cand > svo::kMaxSortedCand ? 2 * pl->max_frames : 0u;
         pl->bvh_depth_cap = bvh_levels(pl->max_cand);
-        pl->bytes = pl->off_bvh + (size_t)pl->max_bvh * sizeof(svo::BvhNode);
+        pl->off_cams = pl->off_bvh + (size_t)pl->max_bvh * sizeof(svo::BvhNode);
+        pl->bytes = pl->off_cams + (size_t)pl->max_jobs * sizeof(svo::CameraArgs);
 
         svo::TraceArgs& a = pl->args;
         a = svo::TraceArgs{};
@@ -1537,7 +1605,9 @@ int svo_plan_set_jobs(svo_ctx* ctx, svo_plan* plan, const svo_job* jobs, uint32_
         std::memcpy(H, &hdr, sizeof hdr);
         write_tables(P, reinterpret_cast<svo::JobRec*>(H + plan->off_jobs), reinterpret_cast<svo::FrameRec*>(H + plan->off_frames),
                      reinterpret_cast<uint32_t*>(H + plan->off_cand), reinterpret_cast<float*>(H + plan->off_sph),
-                     reinterpret_cast<double*>(H + plan->off_x), plan->max_bvh ? reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh) : nullptr, fill);
+                     reinterpret_cast<double*>(H + plan->off_x), plan->max_bvh ? reinterpret_cast<svo::BvhNode*>(H + plan->off_bvh) : nullptr, fill,
+                     reinterpret_cast<svo::CameraArgs*>(H + plan->off_cams),
+                     reinterpret_cast<const svo::CameraArgs*>(plan->dev + plan->off_cams));
         return SVO_OK;
     } catch (const std::bad_alloc&) {
         return fail(SVO_ENOMEM, "out of host memory");
@@ -1740,26 +1810,9 @@ int svo_shade(svo_ctx* ctx, svo_scene scene, const uint32_t* prim_id, const uint
 int svo_generate_primary_rays(svo_ctx* ctx, const svo_camera* cam, float* out_rays, void* stream) {
     if (!ctx || !cam || !out_rays) return fail(SVO_EINVAL, "ctx, cam and out_rays are required");
     if (((uintptr_t)out_rays) & 15u) return fail(SVO_EINVAL, "out_rays must be 16-byte aligned");
-    if (cam->width == 0 || cam->height == 0 || cam->samples == 0) return fail(SVO_EINVAL, "empty image");
-    if (cam->width > kMaxImageSide || cam->height > kMaxImageSide)
-        return fail(SVO_ERANGE, "image sides must be at most %u", kMaxImageSide);
-    if ((uint64_t)cam->width * cam->height * cam->samples > 0xFF000000ull) return fail(SVO_ERANGE, "too many rays");
-    if (!(cam->tan_half_fov > 0.f) || !std::isfinite(cam->tan_half_fov)) return fail(SVO_EINVAL, "bad field of view");
-    svo::CameraArgs c{};
-    for (int a = 0; a < 3; ++a) {
-        c.eye[a] = cam->eye[a];
-        c.fwd[a] = cam->forward[a];
-        c.right[a] = cam->right[a];
-        c.up[a] = cam->up[a];
-    }
-    c.tan_half_fov = cam->tan_half_fov;
-    c.aspect = (float)cam->width / (float)cam->height;
-    c.width = cam->width;
-    c.height = cam->height;
-    c.samples = cam->samples;
-    c.seed = cam->seed;
-    c.jitter = cam->jitter ? 1u : 0u;
-    c.tiled = cam->tiled ? 1u : 0u;
+    svo::CameraArgs c;
+    const int rc = camera_args(cam, c);
+    if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     const hipError_t e = svo::launch_primary_rays(c, out_rays, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SVO_EDEVICE, "ray generation launch failed: %s", hipGetErrorString(e));

@@ -51,8 +51,23 @@ static_assert(sizeof(BvhNode) == 32, "hierarchy node must be 32 bytes");
 constexpr uint32_t kBvhLeaf = 0x80000000u;
 constexpr uint32_t kBvhLeafMax = 2;     // candidates per leaf
 
+// Pinhole camera for primary rays made on the device (see svo_camera.h):
+// by the ray generation kernel, or by the trace kernel for a job that has
+// a camera instead of a ray buffer.  96 bytes.
+struct alignas(16) CameraArgs {
+    float eye[3], fwd[3], right[3], up[3];
+    float tan_half_fov, aspect;
+    uint32_t width, height, samples, seed;
+    uint32_t jitter;      // 0: pixel centres
+    uint32_t tiled;       // 1: 8x8 tile order
+    uint32_t full_tiles;  // tiled, one sample, width and height multiples of 8
+    uint32_t tiles_x;     // width / 8
+    double inv_tiles_x;   // 1 / tiles_x
+};
+static_assert(sizeof(CameraArgs) == 96, "camera record must be 96 bytes");
+
 // One job of a launch: a ray range traced against one scene under one set
-// of transforms (80 bytes, held in LDS).
+// of transforms (96 bytes, held in LDS).
 struct alignas(16) JobRec {
     const uint64_t* nodes;    // the scene's pool
     const float4* rays;       // 2 x float4 per ray
@@ -67,8 +82,10 @@ struct alignas(16) JobRec {
     uint32_t lds_nodes;       // pool prefix of this job's scene held in LDS (0: none)
     uint32_t bvh_base;        // the job's hierarchy root in the launch's node array
     uint32_t n_inline;        // in-place frames, listed after the job's candidates
+    const CameraArgs* cam;    // device camera making the job's rays (rays unused), or nullptr
+    uint64_t pad;
 };
-static_assert(sizeof(JobRec) == 80, "job record must be 80 bytes");
+static_assert(sizeof(JobRec) == 96, "job record must be 96 bytes");
 
 constexpr uint32_t kMaxJobs = 256;
 
@@ -165,6 +182,10 @@ struct TraceArgs {
     uint32_t* counts;
     uint32_t* trail;
     uint32_t trail_cap;
+    // single-job launches: when has_cam0, the job's rays are made from cam0
+    // (job0.rays unused)
+    uint32_t has_cam0;
+    CameraArgs cam0;
 };
 
 struct TraceArgsInline : TraceArgs {
@@ -175,15 +196,6 @@ struct LaunchCfg {
     uint32_t blocks;
     uint32_t waves_per_block;
     size_t lds_bytes;
-};
-
-// Pinhole camera for device-side primary rays (see svo_raygen.hip).
-struct CameraArgs {
-    float eye[3], fwd[3], right[3], up[3];
-    float tan_half_fov, aspect;
-    uint32_t width, height, samples, seed;
-    uint32_t jitter;   // 0: pixel centres
-    uint32_t tiled;    // 1: 8x8 tile order
 };
 
 hipError_t launch_primary_rays(const CameraArgs& c, float* out, hipStream_t stream);

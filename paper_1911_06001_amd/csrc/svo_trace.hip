@@ -41,6 +41,7 @@
 #include <mutex>
 #include <type_traits>
 
+#include "svo_camera.h"
 #include "svo_internal.h"
 
 namespace svo {
@@ -83,11 +84,7 @@ __device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
 // Map the ray into frame F and clip it to the root cell [0, 2^K)^3 and
-// [tmin, tlimit].  Returns false when that interval is empty.  kPrecise:
-// the plane parameters take correctly rounded reciprocals (a walk runs on
-// them, and the error of every plane crossing it compares includes theirs);
-// otherwise the hardware reciprocal (entry tests that only order or cull).
-template <bool kPrecise>
+// [tmin, tlimit].  Returns false when that interval is empty.
 __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, float tlimit, FrameRay& fr, float& t0) {
     const float gx = fmaf(F.m[0], r.ox, fmaf(F.m[1], r.oy, fmaf(F.m[2], r.oz, F.m[3])));
     const float gy = fmaf(F.m[4], r.ox, fmaf(F.m[5], r.oy, fmaf(F.m[6], r.oz, F.m[7])));
@@ -104,15 +101,9 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
     if (fabsf(dy) < eps) dy = copysignf(eps, dy);
     if (fabsf(dz) < eps) dz = copysignf(eps, dz);
     fr.flip = (dx < 0.f ? 1u : 0u) | (dy < 0.f ? 2u : 0u) | (dz < 0.f ? 4u : 0u);
-    if constexpr (kPrecise) {
-        fr.ix = 1.0f / fabsf(dx);
-        fr.iy = 1.0f / fabsf(dy);
-        fr.iz = 1.0f / fabsf(dz);
-    } else {
-        fr.ix = rcp_fast(fabsf(dx));
-        fr.iy = rcp_fast(fabsf(dy));
-        fr.iz = rcp_fast(fabsf(dz));
-    }
+    fr.ix = rcp_fast(fabsf(dx));
+    fr.iy = rcp_fast(fabsf(dy));
+    fr.iz = rcp_fast(fabsf(dz));
     fr.bx = -((dx < 0.f) ? (N - gx) : gx) * fr.ix;
     fr.by = -((dy < 0.f) ? (N - gy) : gy) * fr.iy;
     fr.bz = -((dz < 0.f) ? (N - gz) : gz) * fr.iz;
@@ -237,6 +228,7 @@ __host__ __device__ __forceinline__ size_t align16(size_t v) { return (v + 15) &
 // accessors restore it so the compiler emits global (not generic) loads and
 // stores.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ __forceinline__ T gld(const T* p, uint64_t i) {
@@ -437,7 +429,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         const FrameRec& F = lds_frames[f];
         if (F.info & FR_EMPTY) return false;
         float t0;
-        if (!frame_setup<true>(F, r, tl, fr, t0)) return false;
+        if (!frame_setup(F, r, tl, fr, t0)) return false;
         if constexpr (kCount) {
             ++c_frames;
             ++c_nodes;   // the frame's root record
@@ -480,9 +472,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             if (!sphere_may_hit(lds_sph[f], r, tlim)) return false;
             FrameRay cfr;
             float t0;
-            // the walk's own entry test rounds differently: widened so that
-            // no frame a full trace would walk is ruled out here
-            return frame_setup<false>(lds_frames[f], r, tlim + fabsf(tlim) * 0x1p-18f, cfr, t0);
+            return frame_setup(lds_frames[f], r, tlim, cfr, t0);
         };
         const JobRec& J = lds_jobs[job];
         if (!J.out_inst) return false;
@@ -609,6 +599,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                         c_nodes = c_frames = c_trail = 0;
                     }
                     const float4* rays;
+                    const CameraArgs* cam = nullptr;
                     if constexpr (kSingle) {
                         ri = (uint32_t)(gidx - a.job0.ray_begin);
                         rays = a.job0.rays;
@@ -629,11 +620,37 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                         cbase = J.cand_base;
                         ncand = J.n_cand;
                         rays = J.rays;
+                        cam = J.cam;
                     }
-                    const v4f* rp = reinterpret_cast<const v4f*>(rays);
-                    const v4f r0 = gld(rp, 2 * (uint64_t)ri);
-                    const v4f r1 = gld(rp, 2 * (uint64_t)ri + 1);
-                    r = Ray{r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+                    // the ray: read, or made from the job's camera (Fig. 5:
+                    // one pixel sample per ray)
+                    bool made = false;
+                    if constexpr (kSingle) {
+                        if (a.has_cam0) {
+                            float4 c0, c1;
+                            camera_ray(a.cam0, ri, c0, c1);
+                            r = Ray{c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+                            made = true;
+                        }
+                    } else {
+                        if (cam) {
+                            // 96 bytes from global memory (six 16-byte loads)
+                            v4u w[6];
+                            for (int k = 0; k < 6; ++k) w[k] = gld(reinterpret_cast<const v4u*>(cam), k);
+                            CameraArgs C;
+                            std::memcpy(&C, w, sizeof C);
+                            float4 c0, c1;
+                            camera_ray(C, ri, c0, c1);
+                            r = Ray{c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+                            made = true;
+                        }
+                    }
+                    if (!made) {
+                        const v4f* rp = reinterpret_cast<const v4f*>(rays);
+                        const v4f r0 = gld(rp, 2 * (uint64_t)ri);
+                        const v4f r1 = gld(rp, 2 * (uint64_t)ri + 1);
+                        r = Ray{r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+                    }
                     best_t = INFINITY;
                     best_id = kNone;
                     best_inst = kNone;
@@ -657,7 +674,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                                 if (sphere_may_hit(lds_sph[f], r, tl)) {
                                     FrameRay cfr;
                                     float t0;
-                                    if (frame_setup<false>(lds_frames[f], r, tl, cfr, t0)) e = t0;
+                                    if (frame_setup(lds_frames[f], r, tl, cfr, t0)) e = t0;
                                 }
                                 ent[c * 64] = e;
                             }
@@ -811,7 +828,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 const FrameRec& C = lds_frames[xf];
                 FrameRay cfr;
                 float t0;
-                if (frame_setup<true>(C, r, fminf(tl, xf_tc1), cfr, t0)) {
+                if (frame_setup(C, r, fminf(tl, xf_tc1), cfr, t0)) {
                     if constexpr (kCount) {
                         ++c_frames;
                         ++c_nodes;   // the frame's root record
@@ -851,7 +868,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     py = e.z;
                     pz = e.w;
                     float t0;
-                    frame_setup<true>(lds_frames[cur_f], r, tl, fr, t0);
+                    frame_setup(lds_frames[cur_f], r, tl, fr, t0);
                     size = 1u << (fr.K - lvl);
                     top = sbase + fr.K;
                     pchild = stkc[slot * 64];

@@ -3,7 +3,9 @@ batched into persistent trace launches, admitted by device-memory footprint.
 
 Each request asks for one frame (an animation frame index) of one resident
 scene at some resolution and rays per pixel.  Pools and transform tables stay
-resident; a request only brings its ray and output buffers.
+resident and are counted against the device-memory budget first
+(svo_scene_bytes); a request only brings its ray and output buffers, admitted
+against what is left.
 
   batched  requests are admitted while their footprint fits the budget;
            every step packs up to `max_rays_per_step` rays from the admitted
@@ -241,6 +243,11 @@ class Server:
         # instead of waiting behind its slowest rays
         self.step_streams = [torch.cuda.Stream(device=self.dev) for _ in range(self.inflight_steps)]
         self.frames = {k: 1 + ctx.scene_stats(e.handle).n_slots for k, e in scenes.items()}
+        # the resident pools and transform tables come out of the budget
+        # first; requests are admitted against what is left
+        self.resident_bytes = sum(ctx.scene_bytes(e.handle) for e in scenes.values())
+        if self.resident_bytes >= self.budget:
+            raise ValueError("resident scenes take %d bytes, the budget is %d" % (self.resident_bytes, self.budget))
         self.max_jobs = int(max_jobs)
         # room for at least two jobs of the largest scene per step
         self.max_frames = max(int(max_frames), 2 * max(self.frames.values()))
@@ -319,8 +326,8 @@ class Server:
         active: List[_Active] = []
         inflight = collections.deque()   # (event, [(active, n_rays)])
         results: List[Result] = []
-        sched = Scheduler(self.budget, self.max_rays, self.policy, max_jobs=self.max_jobs, max_frames=self.max_frames,
-                          solo_rays=self.solo_rays)
+        sched = Scheduler(self.budget - self.resident_bytes, self.max_rays, self.policy, max_jobs=self.max_jobs,
+                          max_frames=self.max_frames, solo_rays=self.solo_rays)
         step = 0
         self.scheduler = sched
         t.cuda.synchronize()

@@ -29,7 +29,8 @@ EXPORTS = ("svo_abi_version", "svo_last_error", "svo_create", "svo_destroy", "sv
            "svo_free_scene", "svo_scene_bytes", "svo_get_scene_stats", "svo_set_transforms", "svo_trace_rays",
            "svo_trace_batch", "svo_get_config", "svo_set_config", "svo_tune", "svo_generate_primary_rays",
            "svo_generate_ao_rays", "svo_trace_rays_reuse", "svo_shade", "svo_plan_create", "svo_plan_set_jobs",
-           "svo_plan_launch", "svo_plan_destroy", "svo_trace_batch_static", "svo_trace_rays_counted")
+           "svo_plan_launch", "svo_plan_destroy", "svo_trace_batch_static", "svo_trace_rays_counted",
+           "svo_trace_camera")
 
 
 class SvoError(RuntimeError):
@@ -44,17 +45,17 @@ class PoolInfo(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
-class Job(ctypes.Structure):
-    _fields_ = [("scene", ctypes.c_uint32), ("fwd_3x4", ctypes.c_void_p), ("rays", ctypes.c_void_p),
-                ("n", ctypes.c_uint64), ("out_id", ctypes.c_void_p), ("out_inst", ctypes.c_void_p),
-                ("out_t", ctypes.c_void_p), ("out_normal", ctypes.c_void_p)]
-
-
 class Camera(ctypes.Structure):
     _fields_ = [("eye", ctypes.c_float * 3), ("forward", ctypes.c_float * 3), ("right", ctypes.c_float * 3),
                 ("up", ctypes.c_float * 3), ("tan_half_fov", ctypes.c_float), ("width", ctypes.c_uint32),
                 ("height", ctypes.c_uint32), ("samples", ctypes.c_uint32), ("seed", ctypes.c_uint32),
                 ("jitter", ctypes.c_uint32), ("tiled", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_uint32), ("fwd_3x4", ctypes.c_void_p), ("rays", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("out_id", ctypes.c_void_p), ("out_inst", ctypes.c_void_p),
+                ("out_t", ctypes.c_void_p), ("out_normal", ctypes.c_void_p), ("camera", ctypes.POINTER(Camera))]
 
 
 def make_camera(eye, target, up, vfov_deg, width, height, samples=1, seed=0, jitter=False, tiled=True) -> Camera:
@@ -124,6 +125,7 @@ def lib():
         "svo_trace_batch_static": (I, [P, ctypes.POINTER(Job), U32, P]),
         "svo_trace_rays_reuse": (I, [P, U32, P, U64, P, P, P, P, P, P]),
         "svo_trace_rays_counted": (I, [P, U32, P, U64, P, P, P, P, P, P, U32, P]),
+        "svo_trace_camera": (I, [P, U32, ctypes.POINTER(Camera), P, P, P, P, P]),
         "svo_shade": (I, [P, U32, P, P, U32, U32, U32, U32, U32, U32, U32, P, P]),
         "svo_tune": (I, [P, U32, P, U64, P, ctypes.POINTER(Config)]),
         "svo_generate_primary_rays": (I, [P, ctypes.POINTER(Camera), P, P]),
@@ -216,10 +218,17 @@ def _job_array(jobs):
         if fwd is not None:
             fwd = np.ascontiguousarray(np.asarray(fwd, np.float32).reshape(-1, 12))
             keep.append(fwd)
-        rp, n = _rays_ptr(j["rays"], "job %d rays" % i)
+        cam = j.get("camera")
+        if cam is not None:
+            # rays made in the trace kernel from the camera
+            rp, n = None, int(cam.width) * int(cam.height) * int(cam.samples)
+            keep.append(cam)
+        else:
+            rp, n = _rays_ptr(j["rays"], "job %d rays" % i)
         arr[i] = Job(int(j["scene"]), _np_ptr(fwd) if fwd is not None else None, rp, n,
                      _dptr(j["out_id"], n, "job %d out_id" % i), _dptr(j.get("out_inst"), n, "job %d out_inst" % i),
-                     _dptr(j["out_t"], n, "job %d out_t" % i), _dptr(j.get("out_normal"), 3 * n, "job %d out_normal" % i))
+                     _dptr(j["out_t"], n, "job %d out_t" % i), _dptr(j.get("out_normal"), 3 * n, "job %d out_normal" % i),
+                     ctypes.pointer(cam) if cam is not None else None)
     return arr, keep
 
 
@@ -342,6 +351,22 @@ class Context:
         rp, n = _rays_ptr(sample_rays, "sample_rays")
         _check(lib().svo_tune(self._ptr, int(scene), rp, n, _stream_handle(stream), ctypes.byref(c)))
         return c
+
+    def trace_camera(self, scene: int, cam: Camera, out: Optional[Hits] = None, stream=None,
+                     normals: bool = True) -> Hits:
+        """svo_trace_camera: trace the camera's primary rays, made in the
+        trace kernel (no ray buffer)."""
+        import torch
+        n = cam.width * cam.height * cam.samples
+        dev = "cuda:%d" % self.device
+        if out is None:
+            out = Hits(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+                       torch.empty(n, dtype=torch.float32, device=dev),
+                       torch.empty((n, 3), dtype=torch.float32, device=dev) if normals else None)
+        _check(lib().svo_trace_camera(self._ptr, int(scene), ctypes.byref(cam), _dptr(out.id, n, "out_id"),
+                                      _dptr(out.inst, n, "out_inst"), _dptr(out.t, n, "out_t"),
+                                      _dptr(out.normal, 3 * n, "out_normal"), _stream_handle(stream)))
+        return out
 
     def primary_rays(self, cam: Camera, out=None, stream=None):
         """Generate cam.width * cam.height * cam.samples rays into a device tensor [n, 8]."""

@@ -1,6 +1,7 @@
 """Ceiling kernels (libsvo_ceiling.so): the gather kernel reads exactly the
 words its index streams name (checked against a host replay of the
-SplitMix64 index streams), and the stream kernel folds every word."""
+SplitMix64 index streams, dependent streams salted per stream), and the
+stream kernel folds every word."""
 import sys
 
 import numpy as np
@@ -33,14 +34,16 @@ def _expected_gather(words, blocks, threads, chains, loads, dependent, seed):
     n = len(words)
     out = []
     for tid in range(blocks * threads):
-        st = [(_mix64(seed ^ (tid * chains + c)) & 0xFFFFFFFF) | 1 for c in range(chains)]
+        h = [_mix64(seed ^ (tid * chains + c)) for c in range(chains)]
+        st = [(x & 0xFFFFFFFF) | 1 for x in h]
+        salt = [x >> 32 for x in h]
         acc = 0
         for k in range(loads):
             w = [words[(s * n) >> 32] for s in st]
             for c in range(chains):
                 acc ^= w[c]
                 if dependent:
-                    st[c] = ((((w[c] & 0xFFFFFFFF) ^ (w[c] >> 32)) * 0x9E3779B1 + k) & 0xFFFFFFFF) | 1
+                    st[c] = ((((w[c] & 0xFFFFFFFF) ^ (w[c] >> 32) ^ salt[c]) * 0x9E3779B1 + k) & 0xFFFFFFFF) | 1
                 else:
                     st[c] = _xorshift32(st[c])
         out.append(acc)
