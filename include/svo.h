@@ -126,7 +126,11 @@ typedef struct {
     uint32_t refill_lanes;      /* 0 or 64: a wave takes 64-ray tiles; 1..63: claim new rays once that many lanes are idle */
     uint32_t step_limit;        /* cell advances plus candidate selections per ray before SVO_STEP_LIMIT */
     uint32_t claim_tiles;       /* 64-ray tiles a wave takes from the work queue at once (0: 2; at most 64) */
-    uint32_t reserved[2];
+    uint32_t sorted_candidates; /* 0: 16; 1..64: a job with at most this many candidate frames orders them by
+                                   entry with a per-lane sorted table (the depth sort of Sec. 4.2), one with more
+                                   through the box hierarchy over their world boxes (a scene whose table travels
+                                   in the kernel arguments always takes the sorted table) */
+    uint32_t reserved;          /* zero */
 } svo_config;
 
 /* ABI version the library was built with (SVO_ABI_VERSION). */
@@ -137,11 +141,13 @@ int svo_abi_version(void);
 const char* svo_last_error(void);
 
 /* Create a context on HIP device `device_ordinal` (makes it current while
-   the library works).  *out is set to NULL on failure. */
+   the library works).  *out is set to NULL on failure.  Infrastructure: no
+   passage of the paper defines it. */
 int svo_create(svo_ctx** out, int device_ordinal);
 
 /* Free every scene, buffer and stream resource of the context after
-   waiting for its device work.  NULL is a no-op. */
+   waiting for its device work.  NULL is a no-op.  Infrastructure: no
+   passage of the paper defines it. */
 void svo_destroy(svo_ctx* ctx);
 
 /* Host-only pool check (no device needed).  nodes: host, n_nodes entries.
@@ -158,15 +164,22 @@ int svo_validate(const uint64_t* nodes, uint64_t n_nodes, uint32_t root, uint32_
 /* Validate a pool and copy it to the device (synchronous).  root_min[3],
    root_size: world root cell.  slot_cell: host, n_slots * 4 floats (local
    root cell min xyz, edge length > 0).  Every slot starts with the identity
-   transform.  *out receives the scene handle. */
+   transform.  *out receives the scene handle.  The parent frame of each slot
+   (its nesting) is read from the pool itself: the slot whose subtree holds
+   the transformed node, or the world, so it is not an argument.  The scene
+   of independent SVOs with transforms is the paper's (Sec. 3), placed here
+   on nodes; the upload itself is infrastructure. */
 int svo_upload(svo_ctx* ctx, const uint64_t* nodes, uint64_t n_nodes, uint32_t root, const float root_min[3],
                float root_size, uint32_t max_depth, const uint32_t* slot_child, const float* slot_cell,
                uint32_t n_slots, svo_scene* out);
 
-/* Release a scene's device memory after its queued work has finished. */
+/* Release a scene's device memory after its queued work has finished.
+   Infrastructure: no passage of the paper defines it. */
 int svo_free_scene(svo_ctx* ctx, svo_scene scene);
 
-/* Device bytes the scene holds (pool + transform tables), for admission. */
+/* Device bytes the scene holds (pool + transform tables), for admission.
+   Infrastructure: no passage of the paper defines it (the paper sizes its
+   SVOs and transforms in memory, Sec. 5.2). */
 int svo_scene_bytes(svo_ctx* ctx, svo_scene scene, uint64_t* bytes);
 
 /* Classification of the scene's frames under its latest transforms. */
@@ -182,10 +195,10 @@ int svo_get_scene_stats(svo_ctx* ctx, svo_scene scene, svo_scene_stats* out);
    device work, and every trace keeps the transforms current when it was
    enqueued, on any stream.  A larger scene's table is copied on `stream`;
    traces enqueued on `stream` afterwards see the new transforms, earlier
-   ones the old (two device tables alternate, so the second call after a
-   trace rewrites the table that trace reads: a trace on another stream must
-   have finished before then, which the caller orders; svo_trace_batch jobs
-   that pass their own maps are not affected).  A slot whose moved cell stays
+   ones the old (two device tables alternate; a copy into a table that
+   traces on other streams may still read waits for them on the device, so
+   `stream` may stall behind them but no trace reads a half-written table;
+   svo_trace_batch jobs read the host staging when they are packed).  A slot whose moved cell stays
    inside its static cell (with a margin of 1e-5 cell) is entered in place
    when the walk reaches it (at most SVO_MAX_INLINE_NEST deep); every other
    slot is traced as a separate candidate in order of its root-cell entry.
@@ -410,8 +423,9 @@ int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
 /* Autotuner.  Times candidate kernel configurations on n device sample rays
    against `scene` under its current transforms, in two stages: the launch
    shape (waves per work-group, work-groups per CU, LDS pool-prefix size),
-   then lane refill and tiles per work-queue claim for the fastest shape,
-   then five times longer timings of that winner and the next two shapes.  Keeps
+   then lane refill, tiles per work-queue claim and the candidate ordering
+   (sorted table or hierarchy) for the fastest shape, then five times longer timings of that winner and the next
+   two shapes.  Infrastructure: no passage of the paper defines it.  Keeps
    the fastest for that scene -- later svo_trace_rays calls on it use it, and
    a batch uses it when that scene holds most of the batch's rays -- and
    writes it to *best (nullable).  Results never depend on the

@@ -300,6 +300,10 @@ struct Scene {
     size_t table_bytes = 0;
     bool inline_tab = false;            // small enough for the table to travel in a launch's arguments
     bool dev_current = true;            // the current device table holds the current transforms
+    // traces that read device table k, one event per stream (re-recorded by
+    // later traces on that stream): a copy into table k waits for them all
+    std::vector<std::pair<hipStream_t, hipEvent_t>> readers[2];
+    std::vector<hipEvent_t> spare_events;
     int cur = 0;                        // table the next trace reads
     uint32_t n_frames = 1;              // 1 + n_slots records per table
     // classification of the current table
@@ -390,7 +394,14 @@ int check_config(const svo_config& c) {
     if (c.lds_cache_nodes > 16384) return fail(SVO_EINVAL, "lds_cache_nodes must be <= 16384");
     if (c.step_limit < 1) return fail(SVO_EINVAL, "step_limit must be >= 1");
     if (c.claim_tiles > 64) return fail(SVO_EINVAL, "claim_tiles must be <= 64");
+    if (c.sorted_candidates > 64) return fail(SVO_EINVAL, "sorted_candidates must be <= 64");
+    if (c.reserved) return fail(SVO_EINVAL, "the reserved field must be zero");
     return SVO_OK;
+}
+
+// Candidates up to which a job takes the per-lane sorted entry table.
+uint32_t sort_limit(const svo_config& c) {
+    return c.sorted_candidates ? c.sorted_candidates : svo::kMaxSortedCand;
 }
 
 void free_scene(Scene& s) {
@@ -399,7 +410,11 @@ void free_scene(Scene& s) {
         if (s.d_table[k]) (void)hipFree(s.d_table[k]);
         if (s.h_stage[k]) (void)hipHostFree(s.h_stage[k]);
         if (s.ev[k]) (void)hipEventDestroy(s.ev[k]);
+        for (auto& r : s.readers[k]) (void)hipEventDestroy(r.second);
+        s.readers[k].clear();
     }
+    for (hipEvent_t e : s.spare_events) (void)hipEventDestroy(e);
+    s.spare_events.clear();
     s.d_nodes = nullptr;
 }
 
@@ -670,6 +685,13 @@ int upload_frames(Scene& S, hipStream_t stream, bool to_device) {
     int rc = build_frames(S, S.fwd, S.h_stage[k], T);
     if (rc) return rc;
     if (to_device) {
+        // traces on other streams may still read the table this copy
+        // overwrites: the copy waits for them on the device
+        for (auto& r : S.readers[k]) {
+            if (r.first != stream) HIP_TRY(hipStreamWaitEvent(stream, r.second, 0));
+            S.spare_events.push_back(r.second);
+        }
+        S.readers[k].clear();
         HIP_TRY(hipMemcpyAsync(S.d_table[k], S.h_stage[k], S.table_bytes, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipEventRecord(S.ev[k], stream));
     }
@@ -1230,8 +1252,11 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     a.spheres = reinterpret_cast<const float4*>(S->d_table[S->cur] + sphere_offset(S->n_frames, S->n_slots));
     a.xmaps = reinterpret_cast<const double*>(S->d_table[S->cur] + xmap_offset(S->n_frames, S->n_slots));
     a.bvh = reinterpret_cast<const svo::BvhNode*>(S->d_table[S->cur] + bvh_offset(S->n_frames, S->n_slots));
-    // the hierarchy is walked only past kMaxSortedCand candidates
-    a.n_bvh_total = S->n_cand > svo::kMaxSortedCand ? S->n_bvh : 0u;
+    // the hierarchy is walked only past the configured number of
+    // candidates; a table in the arguments has none, so it takes the sorted
+    // path whatever the count (such scenes have at most 10 slots)
+    const bool sorted = S->n_cand <= sort_limit(cfg) || !S->dev_current;
+    a.n_bvh_total = sorted ? 0u : S->n_bvh;
     a.bvh_depth = S->bvh_depth;
     // transforms changed since the device table was written: the table
     // travels in the arguments
@@ -1254,7 +1279,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     a.lds_nodes = cache;
     a.stack_levels = S->stack_levels;
     a.nest_levels = S->nest_levels;
-    a.sort_cand = S->n_cand <= svo::kMaxSortedCand ? 1u : 0u;
+    a.sort_cand = sorted ? 1u : 0u;
     fill_common(cfg, a);
     a.reuse = reuse ? 1u : 0u;
     a.retraced = retraced;
@@ -1265,7 +1290,26 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
         a.has_cam0 = 1;
         a.cam0 = *cam;
     }
-    return launch(ctx, cfg, a, st, tab, tab_bytes);
+    rc = launch(ctx, cfg, a, st, tab, tab_bytes);
+    if (rc == SVO_OK && !tab) {
+        // this launch reads the current device table: a later copy into it
+        // must wait for the launch
+        auto& rd = S->readers[S->cur];
+        auto it = std::find_if(rd.begin(), rd.end(), [&](const std::pair<hipStream_t, hipEvent_t>& x) { return x.first == st; });
+        if (it == rd.end()) {
+            hipEvent_t e = nullptr;
+            if (!S->spare_events.empty()) {
+                e = S->spare_events.back();
+                S->spare_events.pop_back();
+            } else {
+                HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            }
+            rd.push_back({st, e});
+            it = rd.end() - 1;
+        }
+        HIP_TRY(hipEventRecord(it->second, st));
+    }
+    return rc;
 }
 
 }  // namespace
@@ -1350,7 +1394,8 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
         const size_t cb = bb + (size_t)P.bvh * sizeof(svo::BvhNode);
         const size_t bytes = cb + P.jobs.size() * sizeof(svo::CameraArgs);
         svo::TraceArgs a{};
-        a.n_bvh_total = P.max_cand > svo::kMaxSortedCand ? P.bvh : 0u;
+        const bool sorted = P.max_cand <= sort_limit(cfg);
+        a.n_bvh_total = sorted ? 0u : P.bvh;
         a.bvh_depth = P.bvh_depth;
         a.n_jobs = (uint32_t)P.jobs.size();
         a.n_frames = P.frames;
@@ -1360,7 +1405,7 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
         a.cache_src = P.cache_src;
         a.queue = queue;
         a.lds_nodes = (uint32_t)std::min<uint64_t>(cfg.lds_cache_nodes, cache_pool_nodes) & ~1u;
-        a.sort_cand = P.max_cand <= svo::kMaxSortedCand ? 1u : 0u;
+        a.sort_cand = sorted ? 1u : 0u;
         a.stack_levels = P.stack_levels;
         a.nest_levels = P.nest_levels;
         fill_common(cfg, a);
@@ -1373,7 +1418,7 @@ int trace_batch(svo_ctx* ctx, const svo_job* jobs, uint32_t n_jobs, void* stream
         const size_t lds = fit_lds(ctx, a, cfg.waves_per_block);
         if (lds > ctx->max_lds) return fail(SVO_ERANGE, "batch needs %zu bytes of LDS per work-group", lds);
 
-        if (P.jobs.size() == 1 && P.jobs[0].S->inline_tab) {
+        if (P.jobs.size() == 1 && P.jobs[0].S->inline_tab && a.sort_cand) {
             // one job of a small scene: its table (the scene's layout, frame
             // base 0) travels in the kernel arguments, with no table copy
             const PackedJob& Q = P.jobs[0];
@@ -1514,7 +1559,7 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         pl->off_sph = (pl->off_cand + (size_t)pl->max_frames * sizeof(uint32_t) + 15) & ~(size_t)15;
         pl->off_x = pl->off_sph + (size_t)pl->max_frames * 16;
         pl->off_bvh = pl->off_x + (size_t)pl->max_frames * kXmapBytes;
-        pl->max_bvh = pl->max_cand > svo::kMaxSortedCand ? 2 * pl->max_frames : 0u;
+        pl->max_bvh = pl->max_cand > sort_limit(pl->cfg) ? 2 * pl->max_frames : 0u;
         pl->bvh_depth_cap = bvh_levels(pl->max_cand);
         pl->off_cams = pl->off_bvh + (size_t)pl->max_bvh * sizeof(svo::BvhNode);
         pl->bytes = pl->off_cams + (size_t)pl->max_jobs * sizeof(svo::CameraArgs);
@@ -1527,7 +1572,7 @@ int svo_plan_create(svo_ctx* ctx, const svo_scene* scenes, uint32_t n_scenes, co
         a.n_bvh_total = pl->max_bvh;
         a.bvh_depth = pl->bvh_depth_cap;
         a.max_cand = pl->max_cand;
-        a.sort_cand = pl->max_cand <= svo::kMaxSortedCand ? 1u : 0u;
+        a.sort_cand = pl->max_cand <= sort_limit(pl->cfg) ? 1u : 0u;
         a.stack_levels = pl->stack_cap;
         a.nest_levels = pl->nest_cap;
         a.lds_nodes = (uint32_t)std::min<uint64_t>(pl->cfg.lds_cache_nodes, max_pool) & ~1u;
@@ -1672,8 +1717,9 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
     svo_config win = base;
     float win_ms = 1e30f;
     // Stages: the launch shape (waves per work-group, work-groups per CU,
-    // LDS node cache) at whole-tile refill and 2-tile claims; refill and
-    // claim size for the winning shape; a longer timing of the best three.
+    // LDS node cache) at whole-tile refill and 2-tile claims; refill, claim
+    // size and candidate ordering for the winning shape; a longer timing of
+    // the best three.
     static const uint32_t kWaves[] = {4, 8, 12, 16};
     static const uint32_t kBlocks[] = {1, 2, 3, 4, 5, 6, 8};
     static const uint32_t kCache[] = {1024, 2048, 4096};
@@ -1734,6 +1780,14 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
                 cand.claim_tiles = y;
                 cands.push_back(cand);
             }
+        // the other candidate ordering: the box hierarchy for a scene that
+        // takes the sorted table, the sorted table (up to 64) for one that
+        // takes the hierarchy
+        if (S->n_cand > 1 && S->n_cand <= 64) {
+            svo_config other = shape;
+            other.sorted_candidates = S->n_cand <= sort_limit(shape) ? S->n_cand - 1 : 64u;
+            cands.push_back(other);
+        }
         try_all(cands, false);
     }
     // Short timings are noisy: the winner and the next two shapes of the

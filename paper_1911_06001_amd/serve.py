@@ -130,6 +130,9 @@ class Scheduler:
     A request that is the only one with work left may take up to
     `solo_rays` rays in one step (0: no exception): there is nothing to
     interleave with it, and every extra step costs a launch and its drain.
+    For the same reason a chunk takes the rest of its request's phase when
+    that rest is at most a quarter of the step cap and the chunk stays
+    within 1.25 step caps.
     """
 
     def __init__(self, budget: int, max_rays: int, policy: str = "edf", min_chunk: int = 1 << 16,
@@ -190,6 +193,12 @@ class Scheduler:
             if left <= 0 or len(chunks) >= self.max_jobs or frames + a.frames > self.max_frames:
                 break
             k = min(a.n - a.next_ray, share, left)
+            rest = a.n - a.next_ray - k
+            if 0 < rest <= self.max_rays // 4 and k + rest <= self.max_rays + self.max_rays // 4:
+                # a remainder this small would cost a step (and its drain) of
+                # its own: it rides along, the chunk exceeding the step cap by
+                # at most a quarter
+                k += rest
             chunks.append((a, a.next_ray, a.next_ray + k))
             a.next_ray += k
             a.pending_chunks += 1

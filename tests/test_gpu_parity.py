@@ -286,6 +286,44 @@ def test_small_scene_traces_keep_their_transforms_on_any_stream(ctx, torch_dev):
         parity.assert_parity(parity.compare(parity.to_numpy(hh), ref, ref.margin, rays))
 
 
+def test_large_scene_table_updates_wait_for_traces_on_other_streams(ctx, torch_dev):
+    """A scene above 10 slots keeps two device tables.  A long trace on one
+    stream reads the current table; two transform updates on another stream
+    then rewrite first the other table and then the one that trace reads:
+    the second copy waits for the trace on the device, so the trace still
+    sees the transforms it was enqueued with (checked bit for bit against a
+    trace of the same transforms alone), and the traces after the updates
+    see theirs."""
+    torch = torch_dev
+    sc = S.instanced_scene()
+    rays, _ = sc.rays()                       # 1080p: a launch long enough to overlap the copies
+    r = torch.from_numpy(rays).cuda()
+    h = ctx.upload_scene(sc)
+    try:
+        assert ctx.scene_stats(h).n_candidates > 16
+        f0, f1, f2 = sc.xform(0), sc.xform(0).copy(), sc.xform(0).copy()
+        f1[:, 3] += 1.5                        # translations only: the same slots stay valid
+        f2[:, 7] -= 2.0
+        refs = []
+        for f in (f0, f1, f2):
+            ctx.set_transforms(h, f)
+            refs.append(ctx.trace(h, r))
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Stream(), torch.cuda.Stream()
+        ctx.set_transforms(h, f0, stream=a)
+        a.synchronize()
+        long_trace = ctx.trace(h, r, stream=a)
+        ctx.set_transforms(h, f1, stream=b)    # the other table
+        ctx.set_transforms(h, f2, stream=b)    # the table long_trace reads: waits for it
+        after = ctx.trace(h, r, stream=b)
+        torch.cuda.synchronize()
+        for k in ("id", "inst", "t", "normal"):
+            assert torch.equal(getattr(long_trace, k), getattr(refs[0], k)), k
+            assert torch.equal(getattr(after, k), getattr(refs[2], k)), k
+    finally:
+        ctx.free_scene(h)
+
+
 def test_rejected_transforms_change_nothing(ctx, torch_dev):
     """A call rejected for one slot's map (singular) stores none of its maps:
     a later call that uploads the table again still traces the old ones."""
@@ -448,6 +486,36 @@ def test_results_independent_of_kernel_config(ctx, torch_dev):
     finally:
         ctx.set_config(**base_cfg)
         ctx.free_scene(h)
+
+
+def test_results_independent_of_candidate_ordering(ctx, torch_dev):
+    """sorted_candidates picks the per-lane sorted entry table or the box
+    hierarchy for a job's candidate frames: both give bit-identical results,
+    on a scene of 64 candidates (hierarchy by default, the sorted table up to
+    64) and one of at most 12 (the sorted table by default, the hierarchy
+    below its count)."""
+    torch = torch_dev
+    base_cfg = ctx.get_config().as_dict()
+    cases = [(S.instanced_scene(), 0, None, 64),
+             (S.tiny_scene(5, K=6, n_slots=12, nested=False, scale_range=(0.8, 1.6)), 3, "random", 1)]
+    for sc, frame, kind, other in cases:
+        rays = S.random_rays(4, 20000, 0.0, 64.0) if kind == "random" else sc.rays(W=320, H=180)[0]
+        r = torch.from_numpy(rays).cuda()
+        h = ctx.upload_scene(sc)
+        try:
+            ctx.set_transforms(h, sc.xform(frame))
+            st = ctx.scene_stats(h)
+            assert st.n_candidates > 1, st.n_candidates
+            ctx.set_config(**base_cfg)
+            ref = ctx.trace(h, r)
+            ctx.set_config(sorted_candidates=other)
+            o = ctx.trace(h, r)
+            torch.cuda.synchronize()
+            for k in ("id", "inst", "t", "normal"):
+                assert torch.equal(getattr(o, k), getattr(ref, k)), (sc.name, k)
+        finally:
+            ctx.set_config(**base_cfg)
+            ctx.free_scene(h)
 
 
 def test_step_limit(ctx, torch_dev):

@@ -30,7 +30,8 @@ def _sim(reqs, budget, max_rays, finish_after=2, seed=0, policy="fair", max_jobs
         for a, lo, hi in chunks:
             assert hi - lo > 0
             covered[a.req.rid][lo:hi] += 1
-        assert sum(hi - lo for _, lo, hi in chunks) <= max_rays
+        # a remainder of at most a quarter of the cap rides along
+        assert sum(hi - lo for _, lo, hi in chunks) <= max_rays + max_rays // 4 * len(chunks)
         assert len(chunks) <= max_jobs and sum(a.frames for a, _, _ in chunks) <= 40
         if chunks:
             inflight.append(chunks)
@@ -139,3 +140,20 @@ def test_a_lone_request_takes_up_to_the_solo_cap(policy):
     s4 = Scheduler(1 << 40, 1 << 22, policy=policy)
     a4 = _Active(big, Result(big), None, {}, None)
     assert [(lo, hi) for _, lo, hi in s4.plan([a4])] == [(0, 1 << 22)]
+
+
+@pytest.mark.parametrize("policy", ["fifo", "edf"])
+def test_small_remainder_rides_along(policy):
+    """A chunk that would leave at most a quarter of the step cap takes the
+    rest too (no step of its own for a small tail), within 1.25 caps; a
+    larger remainder waits for the next step."""
+    cap = 1 << 16
+    tail = Request(0, 0.0, "a", 0, 256, 288, 1)          # 73,728 rays = cap + cap / 8
+    far = Request(1, 0.0, "a", 0, 256, 384, 1)           # 98,304 rays = cap + cap / 2
+    s = Scheduler(1 << 40, cap, policy=policy)
+    a = _Active(tail, Result(tail), None, {}, None)
+    chunks = s.plan([a])
+    assert chunks == [(a, 0, tail.rays)]
+    b = _Active(far, Result(far), None, {}, None)
+    chunks = s.plan([b])
+    assert chunks == [(b, 0, cap)]
