@@ -178,8 +178,9 @@ def instances_throughput(ctx, steps, knobs=None):
     ao = ctx.ao_rays(rays, prim, k=4, seed=3, radius=64.0)
     if knobs:
         ctx.set_config(**knobs)
+        cfg = ctx.get_config().as_dict()
     else:
-        ctx.tune(h, rays)
+        cfg = ctx.tune(h, rays).as_dict()
     out_ao = ctx.trace(h, ao)
     stream = torch.cuda.current_stream()
     res = {}
@@ -200,7 +201,8 @@ def instances_throughput(ctx, steps, knobs=None):
     log("instances: primary %.0f Mrays/s, AO %.0f Mrays/s" % (res["primary"]["mrays_per_s"], res["ao"]["mrays_per_s"]))
     res.update({"workload": "instances4096: 64 instances (sphere d8, noise blob d9, heightfield d10, box lattice d11) "
                             "at levels 1-3 of a 4096^3 world; 1920x1080 primary + 4 AO rays per pixel",
-                "nodes": int(sc.nodes.shape[0]), "candidates": int(st.n_candidates), "inline": int(st.n_inline)})
+                "nodes": int(sc.nodes.shape[0]), "candidates": int(st.n_candidates), "inline": int(st.n_inline),
+                "kernel": cfg})
     return res
 
 
