@@ -62,22 +62,30 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(launch_rays: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def read_counters():
+    """Per-launch counter figures from the committed rocprofv3 summary, if it
+    was taken on the current kernel source; else {}."""
     if not os.path.exists(PMC_SUMMARY):
-        return None
+        return {}
     vals = {}
     for line in open(PMC_SUMMARY):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_hash") != kernel_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k, v in vals.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
+# SIMD every 4 cycles (16 lanes per cycle)
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def cpu_baseline(scene, rays, frames, budget_s):
@@ -616,7 +624,8 @@ def main():
     roof = None
     if bytes_per_ray is not None:
         achieved = bytes_per_ray * n / kmean_a / 1e9
-        traffic = read_traffic(n)
+        pmc = read_counters()
+        traffic = pmc.get("hbm_bytes_per_launch")
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "bytes_per_ray": round(bytes_per_ray, 2), "rays_per_launch": n,
@@ -624,6 +633,14 @@ def main():
                 "n_node_mean": round(cb["n_node_mean"], 2), "n_node_p99": round(cb["n_node_p99"], 1),
                 "n_node_upper_mean": round(cb["n_node_hi_mean"], 2),
                 "n_frame_mean": round(cb["n_frame_mean"], 3)}
+        if "valu_wave_insts_per_launch" in pmc:
+            # instruction issue beside the byte roofline: the same launch's VALU
+            # wave instructions (SQ_INSTS_VALU) over its live kernel time
+            vi = pmc["valu_wave_insts_per_launch"]
+            roof["valu_issue"] = {"wave_insts_per_launch": vi, "achieved_G_per_s": round(vi / kmean_a / 1e9, 1),
+                                  "peak_G_per_s": VALU_ISSUE_PEAK / 1e9,
+                                  "frac": round(vi / kmean_a / VALU_ISSUE_PEAK, 4),
+                                  "lane_activity": pmc.get("valu_lane_activity")}
 
     ceilings = None
     if not args.no_ceilings:
