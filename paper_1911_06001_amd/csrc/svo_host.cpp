@@ -324,6 +324,16 @@ struct svo_ctx {
     uint32_t next_scene = 1;
     std::map<uint32_t, std::unique_ptr<Scene>> scenes;
     uint32_t* d_queue = nullptr;                // kMaxStreams work queues of kQueueWords
+    // slow tiles first: two states of kHotWords per work queue, each kept for
+    // one ray set (signature); a state is used from the second trace of its
+    // rays on, so rays traced once pay nothing for it
+    uint32_t* d_hot = nullptr;
+    struct HotRec {
+        uint64_t sig[2] = {0, 0};
+        uint32_t uses[2] = {0, 0};
+        uint32_t recent = 0;    // the state used last (the other one is replaced first)
+    };
+    HotRec hot_rec[kMaxStreams];
     std::map<hipStream_t, uint32_t> stream_slot;
     // ring of batch tables (job records, frames, candidates): pinned staging
     // + device copy, reused once the launch that read them has finished
@@ -395,7 +405,7 @@ int check_config(const svo_config& c) {
     if (c.step_limit < 1) return fail(SVO_EINVAL, "step_limit must be >= 1");
     if (c.claim_tiles > 64) return fail(SVO_EINVAL, "claim_tiles must be <= 64");
     if (c.sorted_candidates > 64) return fail(SVO_EINVAL, "sorted_candidates must be <= 64");
-    if (c.reserved) return fail(SVO_EINVAL, "the reserved field must be zero");
+    if (c.tile_order > 1) return fail(SVO_EINVAL, "tile_order must be 0 or 1");
     return SVO_OK;
 }
 
@@ -762,6 +772,7 @@ int svo_create(svo_ctx** out, int device_ordinal) {
     HIP_TRY(svo::prepare_trace(c->max_lds));
     auto undo = [&](int code, const char* what, hipError_t e) {
         if (c->d_queue) (void)hipFree(c->d_queue);
+        if (c->d_hot) (void)hipFree(c->d_hot);
         if (c->h_static) (void)hipHostFree(c->h_static);
         if (c->static_ev) (void)hipEventDestroy(c->static_ev);
         return fail(code, "%s: %s", what, hipGetErrorString(e));
@@ -770,6 +781,10 @@ int svo_create(svo_ctx** out, int device_ordinal) {
     if (e != hipSuccess) return undo(SVO_ENOMEM, "work queue allocation", e);
     if ((e = hipMemset(c->d_queue, 0, kMaxStreams * svo::kQueueWords * sizeof(uint32_t))) != hipSuccess)
         return undo(SVO_EDEVICE, "work queue clear", e);
+    if ((e = hipMalloc((void**)&c->d_hot, (size_t)kMaxStreams * 2 * svo::kHotWords * sizeof(uint32_t))) != hipSuccess)
+        return undo(SVO_ENOMEM, "slow-tile state allocation", e);
+    if ((e = hipMemset(c->d_hot, 0, (size_t)kMaxStreams * 2 * svo::kHotWords * sizeof(uint32_t))) != hipSuccess)
+        return undo(SVO_EDEVICE, "slow-tile state clear", e);
     // the allocation-free entry point's scratch: found once per device, its
     // queue cleared here (its kernels leave the queue at zero on exit)
     if ((e = svo::static_scratch(device_ordinal, &c->d_static)) != hipSuccess) return undo(SVO_EDEVICE, "scratch lookup", e);
@@ -800,6 +815,7 @@ void svo_destroy(svo_ctx* ctx) {
         if (b.ev) (void)hipEventDestroy(b.ev);
     }
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
+    if (ctx->d_hot) (void)hipFree(ctx->d_hot);
     if (ctx->h_static) (void)hipHostFree(ctx->h_static);
     if (ctx->static_ev) (void)hipEventDestroy(ctx->static_ev);
     delete ctx;
@@ -1056,6 +1072,23 @@ void fill_common(const svo_config& c, svo::TraceArgs& a) {
     a.step_limit = c.step_limit;
 }
 
+// Signature of a ray set, to tell whether a launch traces the rays of the
+// previous one on its queue (FNV-1a over scene, ray pointer, count and
+// camera record).
+uint64_t ray_signature(svo_scene scene, const float* rays, uint64_t n, const svo::CameraArgs* cam) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t len) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    const uintptr_t rp = (uintptr_t)rays;
+    mix(&scene, sizeof scene);
+    mix(&rp, sizeof rp);
+    mix(&n, sizeof n);
+    if (cam) mix(cam, sizeof *cam);
+    return h | 1u;   // never the zero of a cleared state
+}
+
 // Validate a camera and fill the device record (svo_camera.h).
 int camera_args(const svo_camera* cam, svo::CameraArgs& c) {
     if (!cam) return fail(SVO_EINVAL, "camera is NULL");
@@ -1289,6 +1322,26 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
     if (cam) {
         a.has_cam0 = 1;
         a.cam0 = *cam;
+    }
+    // slow tiles first (whole-tile claims): the queue's state carries them
+    // from the previous launch of the same rays
+    const uint64_t tiles = (n + 63) / 64;
+    if (cfg.tile_order == 0 && a.refill == 64 && tiles <= svo::kHotMaxTiles) {
+        const uint64_t sig = ray_signature(scene, rays, n, cam);
+        auto& R = ctx->hot_rec[qslot];
+        uint32_t k = R.sig[0] == sig ? 0u : (R.sig[1] == sig ? 1u : 2u);
+        if (k == 2u) {
+            k = R.recent ^ 1u;
+            R.sig[k] = sig;
+            R.uses[k] = 0;
+        }
+        R.recent = k;
+        if (R.uses[k] < 2u) ++R.uses[k];
+        if (R.uses[k] >= 2u) {
+            a.hot = ctx->d_hot + (size_t)svo::kHotWords * (2u * qslot + k);
+            a.hot_target = (uint32_t)std::min<uint64_t>(svo::kHotCap, std::max<uint64_t>(16, tiles / 25));
+            a.hot_sig = sig;
+        }
     }
     rc = launch(ctx, cfg, a, st, tab, tab_bytes);
     if (rc == SVO_OK && !tab) {

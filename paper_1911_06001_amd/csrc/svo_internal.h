@@ -105,6 +105,26 @@ constexpr uint32_t kQueueWords = kQueueFinished + kQueueStride;
 // Scratch of the allocation-free batched entry point: one work queue, then
 // a table area for the launch's job, frame, candidate, sphere, exact-map and
 // hierarchy records.  One copy per device, in the library's code object.
+// Slow tiles first: per work queue, device state that carries the tiles one
+// launch found slow to the next launch on the same queue (the same rays traced
+// again, as in an animation with a fixed camera).  A tile's cost is the most
+// walk loop iterations (descents and advances) any of its rays took; a launch lists the tiles whose cost is at
+// or above a threshold, and the next launch deals them out to its waves first
+// (no shared counter: wave w takes entries w, w + waves, ...) while its
+// regular claim order skips them.  The threshold follows a target count.
+// Words: [0] which of the two lists is the input, [1] the threshold (0: not
+// yet set), [2 + b] list b's count (raw, may pass kHotCap), [4 + 2b, 5 + 2b]
+// the signature of the launch that wrote list b, then list 0, list 1 (tile
+// indices), bitmap 0, bitmap 1 (a bit per tile of the launch that wrote it).
+constexpr uint32_t kHotCap = 8192;
+constexpr uint32_t kHotMaxTiles = 1u << 18;      // launches with more tiles keep the plain order
+constexpr uint32_t kHotBitsWords = kHotMaxTiles / 32;
+constexpr uint32_t kHotHdr = 16;
+constexpr uint32_t kHotWords = kHotHdr + 2 * kHotCap + 2 * kHotBitsWords;
+constexpr uint32_t kHotPerBlock = 63;            // tiles a work-group can list (LDS); more are dropped
+constexpr size_t kHotLdsBytes = 256;
+constexpr uint32_t kHotInitialThreshold = 64;
+
 constexpr size_t kStaticQueueBytes = ((size_t)kQueueWords * 4 + 255) & ~(size_t)255;
 constexpr size_t kStaticTableBytes = (size_t)256 << 10;
 constexpr size_t kStaticScratchBytes = kStaticQueueBytes + kStaticTableBytes;
@@ -169,6 +189,12 @@ struct TraceArgs {
     unsigned long long* retraced;  // reuse: rays traced again are added here (nullable)
     uint64_t tile_stride;     // claim i covers tile (i * tile_stride) mod tiles (coprime: a permutation)
     uint32_t step_limit;
+    // slow tiles first (one-job launches with whole-tile refill; nullptr:
+    // plain order): this queue's state (kHotWords), the target count of
+    // listed tiles, and the signature of this launch's rays
+    uint32_t* hot;
+    uint32_t hot_target;
+    uint64_t hot_sig;
     // TraceArgsInline launches: frames, cand, spheres and exact maps are read
     // from the inline table at these byte offsets instead of the pointers above
     uint32_t inline_off_cand, inline_off_sph, inline_off_x;

@@ -128,6 +128,16 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
     return te <= fminf(tx, tlimit);
 }
 
+// Slow-tiles-first state (see kHotHdr): which list is the input, the
+// threshold, a list's tiles and its bitmap.  The header stays fixed during a
+// launch until its last work-group rewrites it.
+__device__ __forceinline__ uint32_t hot_in(const uint32_t* hot) { return hot[0] & 1u; }
+__device__ __forceinline__ uint32_t hot_thr(const uint32_t* hot) { return hot[1] ? hot[1] : kHotInitialThreshold; }
+__device__ __forceinline__ uint32_t* hot_list(uint32_t* hot, uint32_t b) { return hot + kHotHdr + b * kHotCap; }
+__device__ __forceinline__ uint32_t* hot_bits(uint32_t* hot, uint32_t b) {
+    return hot + kHotHdr + 2 * kHotCap + b * kHotBitsWords;
+}
+
 // The hit the walk found, checked and measured in FP64.  The walk decides
 // in FP32 which cell the ray meets first; its plane crossings carry an
 // error that grows with the coordinates (frame map, reciprocal direction,
@@ -262,7 +272,7 @@ __host__ __device__ __forceinline__ size_t cand_lane_bytes(const TraceArgs& a) {
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
     const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 80 +
                           align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec) +
-                          (size_t)a.n_bvh_total * sizeof(BvhNode);
+                          (size_t)a.n_bvh_total * sizeof(BvhNode) + (a.hot ? kHotLdsBytes : 0);
     const size_t per_wave = cand_lane_bytes(a) * 64 + (size_t)a.stack_levels * 64 * 5 + (size_t)a.nest_levels * 64 * 16;
     return shared + per_wave * waves_per_block;
 }
@@ -299,6 +309,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     p += (size_t)a.n_jobs * sizeof(JobRec);
     BvhNode* lds_bvh = reinterpret_cast<BvhNode*>(p);
     p += (size_t)a.n_bvh_total * sizeof(BvhNode);
+    // slow tiles this work-group found: count, then up to kHotPerBlock tiles
+    uint32_t* lds_hot = reinterpret_cast<uint32_t*>(p);
+    if (a.hot) p += kHotLdsBytes;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     const size_t ent_bytes = cand_lane_bytes(a) * 64;
@@ -378,6 +391,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     } else if (threadIdx.x == 0) {
         lds_jobs[0] = a.job0;
     }
+    if (a.hot && threadIdx.x == 0) lds_hot[0] = 0u;
     __syncthreads();
 
     const uint32_t refill = a.refill;
@@ -388,6 +402,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     const uint32_t part_len = (uint32_t)((n_tiles + kQueueParts - 1) / kQueueParts) * 64u;
     uint32_t q = (blockIdx.x * wpb + wave) % kQueueParts, rlo = 0, rhi = 0;
     uint64_t known_dry = 0;  // partitions this wave knows to be dry
+    // slow tiles first: the previous launch's list is this launch's input if
+    // it traced the same rays (same signature); this launch's own slow tiles
+    // go to the other list.  The state's header words stay fixed until the
+    // last work-group out rewrites them, so they are read again where needed
+    // rather than kept in registers.
+    uint32_t* hot = a.hot;
+    if (a.hdr || a.jobs || n_tiles > kHotMaxTiles) hot = nullptr;
+    uint32_t hin = 0;   // input tiles to deal out (0 unless the input list is of these rays)
+    if (hot) {
+        const uint32_t b = hot_in(hot);
+        if (((uint64_t)hot[4 + 2 * b] | ((uint64_t)hot[5 + 2 * b] << 32)) == a.hot_sig) hin = min(hot[2 + b], kHotCap);
+    }
 
     // per-lane state
     uint32_t mode = M_DONE;
@@ -403,6 +429,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     uint32_t best_id = kNone, best_inst = kNone;
     int best_f = -1, best_axis = 3;
     uint32_t steps = 0;
+    uint32_t work = 0;   // walk loop iterations of the current ray (visits: descents and advances)
     // the hierarchy walk over the candidates, packed (a job has at most 1023
     // candidates): bits 0-10 next item of the current leaf, 11-21 the
     // leaf's end, 22-31 stack depth
@@ -423,6 +450,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // is itself a solid leaf (recorded where every walk hit is)
     uint32_t pend = 0;
     bool exhausted = !active;  // wave-uniform
+    // slow tiles first (wave-uniform): the next input entry this wave takes
+    // (entries are dealt out over the active waves), and the tile its lanes
+    // are tracing (whole-tile refill)
+    uint32_t hot_k = blockIdx.x * wpb + wave;
+    uint32_t cur_tile = 0xFFFFFFFFu;
 
     auto record_hit = [&](float t, uint32_t id, uint32_t f, int axis) {
         const uint32_t inst = lds_frames[f].inst;
@@ -560,11 +592,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         // ---------------------------------------------------------- refill
         const uint64_t idle = __ballot(mode == M_DONE);
         const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (hot && nidle == 64u && cur_tile != 0xFFFFFFFFu) {
+            // the wave's tile is done (whole tiles): listed when its slowest
+            // ray took at least the threshold's walk loop iterations
+            uint32_t m = work;
+            for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+            if (m >= hot_thr(hot) && lane == 0u) {
+                const uint32_t i = atomicAdd(lds_hot, 1u);
+                if (i < kHotPerBlock) lds_hot[1 + i] = cur_tile;
+            }
+            cur_tile = 0xFFFFFFFFu;
+        }
         if (exhausted && nidle == 64u) break;
         if (!exhausted && nidle >= refill) {
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)idle) - 1u;
             bool retrace = false;
-            if (rlo >= rhi) {
+            if (hot) work = 0;  // lanes left without a ray in the next tile count nothing
+            bool got_hot = false;
+            uint32_t htile = 0;
+            if (hot_k < hin && rlo >= rhi) {
+                got_hot = true;
+                htile = hot_list(hot, hot_in(hot))[hot_k];
+                hot_k += n_active * wpb;
+            }
+            if (!got_hot && rlo >= rhi) {
                 // claim the next range of partition q.  A dry partition is
                 // marked in the shared bitmap by the first wave to overflow
                 // it, so a set bit always means dry (an unset one may be
@@ -597,16 +648,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     rhi = min(base + claim, part_len);
                 }
             }
-            const uint32_t take = (rlo < rhi) ? min(nidle, rhi - rlo) : 0u;
+            const uint32_t take = got_hot ? min(nidle, 64u) : ((rlo < rhi) ? min(nidle, rhi - rlo) : 0u);
             const uint32_t first = rlo;
-            rlo += take;
+            if (!got_hot) rlo += take;
+            // a regular claim's tile (whole tiles: the same for every lane)
+            // and the input bitmap's word for it, tested once the rays'
+            // loads are on their way
+            const uint64_t csl = (uint64_t)(first >> 6) * kQueueParts + q;
+            const uint64_t ctile = hot ? (csl * tstride) % n_tiles : 0u;
+            uint32_t cword = 0;
+            if (hot && take && !got_hot && hin) cword = hot_bits(hot, hot_in(hot))[ctile >> 5];
             if (mode == M_DONE) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 const uint32_t j = first + rank;
                 const uint64_t slot = (uint64_t)(j >> 6) * kQueueParts + q;     // claim order
                 uint64_t gidx = n_rays;
-                if (rank < take && slot < n_tiles) gidx = ((slot * tstride) % n_tiles) * 64u + (j & 63u);
+                if (got_hot) {
+                    if (rank < take && htile < n_tiles) gidx = (uint64_t)htile * 64u + rank;
+                } else if (rank < take && slot < n_tiles) {
+                    gidx = ((slot * tstride) % n_tiles) * 64u + (j & 63u);
+                }
                 if (gidx < n_rays) {
                     if constexpr (kCount) {
                         gray = (uint32_t)gidx;
@@ -671,11 +733,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     best_f = -1;
                     best_axis = 3;
                     steps = 0;
+                    work = 0;
                     bws = 0;
+                    // a tile of the input list was traced by the wave it was dealt to
+                    const bool dealt = !got_hot && ((cword >> (ctile & 31u)) & 1u);
                     bool keep = false;
-                    if (a.reuse && ray_valid(r)) keep = previous_stands();
-                    if (keep) {
-                        // the previous result stands: nothing to trace or write
+                    if (!dealt && a.reuse && ray_valid(r)) keep = previous_stands();
+                    if (dealt || keep) {
+                        // nothing to trace or write: dealt to another wave, or
+                        // the previous result stands
                     } else if (!ray_valid(r)) {
                         finish();
                     } else {
@@ -704,6 +770,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                         mode = start_frame(fbase) ? M_WALK : M_SELECT;
                     }
                 }
+            }
+            if (hot && take) {
+                if (got_hot) cur_tile = htile < n_tiles ? htile : 0xFFFFFFFFu;
+                else cur_tile = (csl < n_tiles && !((cword >> (ctile & 31u)) & 1u)) ? (uint32_t)ctile : 0xFFFFFFFFu;
             }
             if (a.reuse && a.retraced) {
                 const uint64_t re = __ballot(retrace);
@@ -759,6 +829,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             }
             // the hot loop: visit, descend or advance until something happens
             while (ev == EV_NONE) {
+                ++work;
                 const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
                 const float ey = fmaf((float)(py + size), fr.iy, fr.by);
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
@@ -986,15 +1057,57 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // touches no counter, and skipping its atomic spares the others a
     // same-address queue)
     __syncthreads();
+    const uint32_t hp = hot ? hot_in(hot) : 0u, ob = hp ^ 1u;
+    if (hot && active && threadIdx.x == 0) {
+        // this work-group's slow tiles into the output list and its bitmap
+        const uint32_t n = min(lds_hot[0], kHotPerBlock);
+        if (n) {
+            const uint32_t base = atomicAdd(hot + 2 + ob, n);
+            uint32_t* olist = hot_list(hot, ob);
+            uint32_t* obits = hot_bits(hot, ob);
+            for (uint32_t i = 0; i < n && base + i < kHotCap; ++i) {
+                const uint32_t t = lds_hot[1 + i];
+                olist[base + i] = t;
+                atomicOr(obits + (t >> 5), 1u << (t & 31u));
+            }
+        }
+    }
     if (active && threadIdx.x == 0) {
         __threadfence();
         uint32_t* fin = a.queue + kQueueFinished;
         const uint32_t prev = atomicAdd(fin, 1u);
-        if (prev == n_active - 1) {
+        const bool last = prev == n_active - 1;
+        if (last) {
             for (uint32_t p = 0; p < kQueueParts; ++p) atomicExch(a.queue + p * kQueueStride, 0u);
             atomicExch(a.queue + kQueueDry, 0u);
             atomicExch(a.queue + kQueueDry + 1, 0u);
             atomicExch(fin, 0u);
+        }
+        if (hot) lds_hot[0] = last ? 1u : 0u;
+    }
+    if (hot) {
+        __syncthreads();
+        if (active && lds_hot[0]) {
+            // last out (every other work-group has written its list): clear
+            // the input list's bitmap words, which hold only its tiles' bits
+            const uint32_t icount = min(hot[2 + hp], kHotCap);
+            const uint32_t* ilist = hot_list(hot, hp);
+            uint32_t* ibits = hot_bits(hot, hp);
+            for (uint32_t i = threadIdx.x; i < icount; i += blockDim.x) ibits[min(ilist[i], kHotMaxTiles - 1u) >> 5] = 0u;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // the threshold follows the target count of listed tiles
+                const uint32_t c = atomicAdd(hot + 2 + ob, 0u);
+                const uint32_t tg = a.hot_target, hthr = hot_thr(hot);
+                uint32_t nt = hthr;
+                if (c > tg + tg / 2u) nt = hthr + max(1u, hthr / 8u);
+                else if (2u * c < tg && hthr > 1u) nt = hthr - max(1u, hthr / 8u);
+                atomicExch(hot + 4 + 2 * ob, (uint32_t)a.hot_sig);
+                atomicExch(hot + 5 + 2 * ob, (uint32_t)(a.hot_sig >> 32));
+                atomicExch(hot + 2 + hp, 0u);
+                atomicExch(hot + 1, nt);
+                atomicExch(hot + 0, ob);
+            }
         }
     }
 }

@@ -91,7 +91,7 @@ class Config(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("lds_cache_nodes", ctypes.c_uint32), ("refill_lanes", ctypes.c_uint32),
                 ("step_limit", ctypes.c_uint32), ("claim_tiles", ctypes.c_uint32),
-                ("sorted_candidates", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("sorted_candidates", ctypes.c_uint32), ("tile_order", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

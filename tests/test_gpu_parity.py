@@ -677,3 +677,44 @@ def test_hierarchy_over_many_candidates(ctx, torch_dev, n_slots):
     finally:
         ctx.free_scene(h)
         ctx.free_scene(hs)
+
+
+def test_slow_tiles_first_keeps_results(ctx, torch_dev):
+    """tile_order 0 hands the tiles that were slowest in the previous trace of
+    the same rays (on the same stream) to the waves first; tile_order 1 keeps
+    the plain claim order.  Two ray sets traced in turn, the transforms
+    changing between traces: from the third trace of a set on, its own list
+    is in use, and every result equals the plain order's bit for bit.  The
+    counting build, ordered the same way, writes every ray exactly once."""
+    torch = torch_dev
+    sc = S.fbm_terrain_d10()
+    sets = [torch.from_numpy(sc.rays(W=320, H=180)[0]).cuda(),
+            torch.from_numpy(S.random_rays(9, 30000, 0.0, sc.root_size)).cuda()]
+    h = ctx.upload_scene(sc)
+    base_cfg = ctx.get_config().as_dict()
+    try:
+        frames = (0, 7, 14, 21, 28)
+        ctx.set_config(waves_per_block=4, blocks_per_cu=2, lds_cache_nodes=1024, refill_lanes=0, tile_order=1)
+        ref = {}
+        for f in frames:
+            ctx.set_transforms(h, sc.xform(f))
+            for i, r in enumerate(sets):
+                ref[f, i] = ctx.trace(h, r)
+        ctx.set_config(tile_order=0)
+        for rep in range(3):
+            for f in frames:
+                ctx.set_transforms(h, sc.xform(f))
+                for i, r in enumerate(sets):
+                    o = ctx.trace(h, r)
+                    torch.cuda.synchronize()
+                    e = ref[f, i]
+                    assert torch.equal(o.id, e.id) and torch.equal(o.inst, e.inst), (rep, f, i)
+                    assert torch.equal(o.t, e.t) and torch.equal(o.normal, e.normal), (rep, f, i)
+        for i, r in enumerate(sets):
+            hits, counts, _ = ctx.trace_counted(h, r)
+            torch.cuda.synchronize()
+            assert int(counts[2].min()) == 1 and int(counts[2].max()) == 1, i
+            assert torch.equal(hits.id, ref[frames[-1], i].id), i
+    finally:
+        ctx.set_config(**base_cfg)
+        ctx.free_scene(h)
