@@ -108,21 +108,48 @@ constexpr uint32_t kQueueWords = kQueueFinished + kQueueStride;
 // Slow tiles first: per work queue, device state that carries the tiles one
 // launch found slow to the next launch on the same queue (the same rays traced
 // again, as in an animation with a fixed camera).  A tile's cost is the most
-// walk loop iterations (descents and advances) any of its rays took; a launch lists the tiles whose cost is at
-// or above a threshold, and the next launch deals them out to its waves first
-// (no shared counter: wave w takes entries w, w + waves, ...) while its
-// regular claim order skips them.  The threshold follows a target count.
+// advances (moves from a cell to the next, the counter the step limit already
+// keeps) any of its rays took; a launch lists the tiles whose cost is at or
+// above a threshold, and the next launch deals them out to its waves first (no
+// shared counter: wave w takes entries w, w + waves, ...) while its regular
+// claim order skips them.  The threshold follows a target count.  A list is
+// only dealt out when the launch that wrote it was bound by its slowest tiles:
+// when its costliest tile cost at least 0.7 times the mean work of a wave (all
+// tile costs over the active waves); launches of many short tiles per wave
+// keep the plain order.  Work-groups add to the counts on kHotSub separate
+// cache lines (work-group g on line g mod kHotSub), so that no address takes
+// every work-group's atomic at the end of a launch; each line has its own
+// sub-list.
 // Words: [0] which of the two lists is the input, [1] the threshold (0: not
-// yet set), [2 + b] list b's count (raw, may pass kHotCap), [4 + 2b, 5 + 2b]
-// the signature of the launch that wrote list b, then list 0, list 1 (tile
-// indices), bitmap 0, bitmap 1 (a bit per tile of the launch that wrote it).
-constexpr uint32_t kHotCap = 8192;
+// yet set), [4 + 2b, 5 + 2b] the signature of the launch that wrote list b,
+// [10 + b] whether list b is to be dealt out, [12 + b] the tile count of the
+// launch that wrote it; then per line s: list b's count (raw, may pass
+// kHotSubCap) at hot_cnt(b, s), this launch's sum and largest of tile costs
+// at hot_sum(s) and hot_max(s); then list 0, list 1 (kHotSub sub-lists of
+// kHotSubCap tile indices each), bitmap 0, bitmap 1 (a bit per tile of the
+// launch that wrote it).
+constexpr uint32_t kHotSub = 8;
+constexpr uint32_t kHotLine = 32;                // words per cache line (128 B)
+constexpr uint32_t kHotSubCap = 1024;
+constexpr uint32_t kHotCap = kHotSub * kHotSubCap;
 constexpr uint32_t kHotMaxTiles = 1u << 18;      // launches with more tiles keep the plain order
 constexpr uint32_t kHotBitsWords = kHotMaxTiles / 32;
-constexpr uint32_t kHotHdr = 16;
+constexpr uint32_t kHotCntBase = kHotLine;                                  // 2 kHotSub lines
+constexpr uint32_t kHotSumBase = kHotCntBase + 2 * kHotSub * kHotLine;      // kHotSub lines
+constexpr uint32_t kHotMaxBase = kHotSumBase + kHotSub * kHotLine;          // kHotSub lines
+constexpr uint32_t kHotHdr = kHotMaxBase + kHotSub * kHotLine;
 constexpr uint32_t kHotWords = kHotHdr + 2 * kHotCap + 2 * kHotBitsWords;
-constexpr uint32_t kHotPerBlock = 63;            // tiles a work-group can list (LDS); more are dropped
+// A tile's cost enters the sum and the largest cost clamped to kHotCostClamp,
+// so that a launch's sum (at most kHotMaxTiles tiles) fits 32 bits.
+constexpr uint32_t kHotCostClamp = 4095;
+// Per work-group LDS: [0] tiles listed, [1] sum and [2] largest of its tile
+// costs, [3] the input list, [4] the threshold, [5] the input entries to deal
+// out (0: none), [6 + s] sub-list s's count; then up to kHotPerBlock listed
+// tiles from kHotLdsHdr on (more are dropped).
+constexpr uint32_t kHotLdsHdr = 16;
 constexpr size_t kHotLdsBytes = 256;
+constexpr uint32_t kHotPerBlock = kHotLdsBytes / 4 - kHotLdsHdr;
+static_assert(6 + kHotSub <= kHotLdsHdr, "slow-tile LDS header too small");
 constexpr uint32_t kHotInitialThreshold = 64;
 
 constexpr size_t kStaticQueueBytes = ((size_t)kQueueWords * 4 + 255) & ~(size_t)255;

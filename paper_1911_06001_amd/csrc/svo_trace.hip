@@ -133,9 +133,28 @@ __device__ __forceinline__ bool frame_setup(const FrameRec& F, const Ray& r, flo
 // launch until its last work-group rewrites it.
 __device__ __forceinline__ uint32_t hot_in(const uint32_t* hot) { return hot[0] & 1u; }
 __device__ __forceinline__ uint32_t hot_thr(const uint32_t* hot) { return hot[1] ? hot[1] : kHotInitialThreshold; }
+__device__ __forceinline__ uint32_t* hot_cnt(uint32_t* hot, uint32_t b, uint32_t s) {
+    return hot + kHotCntBase + (b * kHotSub + s) * kHotLine;
+}
+__device__ __forceinline__ uint32_t* hot_sum(uint32_t* hot, uint32_t s) { return hot + kHotSumBase + s * kHotLine; }
+__device__ __forceinline__ uint32_t* hot_max(uint32_t* hot, uint32_t s) { return hot + kHotMaxBase + s * kHotLine; }
 __device__ __forceinline__ uint32_t* hot_list(uint32_t* hot, uint32_t b) { return hot + kHotHdr + b * kHotCap; }
 __device__ __forceinline__ uint32_t* hot_bits(uint32_t* hot, uint32_t b) {
     return hot + kHotHdr + 2 * kHotCap + b * kHotBitsWords;
+}
+
+// The largest of a wave's 64 values, wave-uniform: within each row of 16
+// lanes by DPP moves (swap neighbours, swap pairs, mirror the half-rows,
+// mirror the rows), then over the four rows by lane reads.  Every lane must
+// be active.
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    const uint32_t r = max(max((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16)),
+                           max((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48)));
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)r);
 }
 
 // The hit the walk found, checked and measured in FP64.  The walk decides
@@ -309,7 +328,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     p += (size_t)a.n_jobs * sizeof(JobRec);
     BvhNode* lds_bvh = reinterpret_cast<BvhNode*>(p);
     p += (size_t)a.n_bvh_total * sizeof(BvhNode);
-    // slow tiles this work-group found: count, then up to kHotPerBlock tiles
+    // slow tiles this work-group found: count, sum and largest of its tile
+    // costs, then up to kHotPerBlock tiles
     uint32_t* lds_hot = reinterpret_cast<uint32_t*>(p);
     if (a.hot) p += kHotLdsBytes;
     const uint32_t lane = threadIdx.x & 63u;
@@ -391,29 +411,47 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     } else if (threadIdx.x == 0) {
         lds_jobs[0] = a.job0;
     }
-    if (a.hot && threadIdx.x == 0) lds_hot[0] = 0u;
+    // slow tiles first: the previous launch's list is this launch's input if
+    // it traced the same rays (same signature); this launch's own slow tiles
+    // go to the other list.  The state's header words stay fixed until the
+    // last work-group out rewrites them, so each work-group reads them once
+    // into its LDS header.
+    const uint64_t n_tiles = (n_rays + 63) >> 6;
+    uint32_t* hot = a.hot;
+    if (a.hdr || a.jobs || n_tiles > kHotMaxTiles) hot = nullptr;
+    if (hot && threadIdx.x < kHotLdsHdr) {
+        // one round of loads: the words of both lists, then the input's
+        const uint32_t t = threadIdx.x, b = hot_in(hot);
+        uint32_t v = 0;
+        if (t == 3) {
+            v = b;
+        } else if (t == 4) {
+            v = hot_thr(hot);
+        } else if (t == 5) {
+            uint32_t c0 = 0, c1 = 0;
+            for (uint32_t k = 0; k < kHotSub; ++k) {
+                c0 = max(c0, *hot_cnt(hot, 0, k));
+                c1 = max(c1, *hot_cnt(hot, 1, k));
+            }
+            const bool d0 = hot[10] && ((uint64_t)hot[4] | ((uint64_t)hot[5] << 32)) == a.hot_sig;
+            const bool d1 = hot[11] && ((uint64_t)hot[6] | ((uint64_t)hot[7] << 32)) == a.hot_sig;
+            // entry e is sub-list e mod kHotSub's (e / kHotSub)-th
+            if (b ? d1 : d0) v = min(b ? c1 : c0, kHotSubCap) * kHotSub;
+        } else if (t >= 6 && t < 6 + kHotSub) {
+            const uint32_t c0 = *hot_cnt(hot, 0, t - 6), c1 = *hot_cnt(hot, 1, t - 6);
+            v = min(b ? c1 : c0, kHotSubCap);
+        }
+        lds_hot[t] = v;
+    }
     __syncthreads();
 
     const uint32_t refill = a.refill;
     const uint32_t claim = a.claim;
     // partition-local ray indices run to part_len (whole tiles); a wave owns
     // the claimed range [rlo, rhi) of partition q (wave-uniform state)
-    const uint64_t n_tiles = (n_rays + 63) >> 6;
     const uint32_t part_len = (uint32_t)((n_tiles + kQueueParts - 1) / kQueueParts) * 64u;
     uint32_t q = (blockIdx.x * wpb + wave) % kQueueParts, rlo = 0, rhi = 0;
     uint64_t known_dry = 0;  // partitions this wave knows to be dry
-    // slow tiles first: the previous launch's list is this launch's input if
-    // it traced the same rays (same signature); this launch's own slow tiles
-    // go to the other list.  The state's header words stay fixed until the
-    // last work-group out rewrites them, so they are read again where needed
-    // rather than kept in registers.
-    uint32_t* hot = a.hot;
-    if (a.hdr || a.jobs || n_tiles > kHotMaxTiles) hot = nullptr;
-    uint32_t hin = 0;   // input tiles to deal out (0 unless the input list is of these rays)
-    if (hot) {
-        const uint32_t b = hot_in(hot);
-        if (((uint64_t)hot[4 + 2 * b] | ((uint64_t)hot[5 + 2 * b] << 32)) == a.hot_sig) hin = min(hot[2 + b], kHotCap);
-    }
 
     // per-lane state
     uint32_t mode = M_DONE;
@@ -429,7 +467,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     uint32_t best_id = kNone, best_inst = kNone;
     int best_f = -1, best_axis = 3;
     uint32_t steps = 0;
-    uint32_t work = 0;   // walk loop iterations of the current ray (visits: descents and advances)
     // the hierarchy walk over the candidates, packed (a job has at most 1023
     // candidates): bits 0-10 next item of the current leaf, 11-21 the
     // leaf's end, 22-31 stack depth
@@ -455,6 +492,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // are tracing (whole-tile refill)
     uint32_t hot_k = blockIdx.x * wpb + wave;
     uint32_t cur_tile = 0xFFFFFFFFu;
+    uint32_t tc_sum = 0, tc_max = 0;   // the wave's tile costs (clamped)
+    // launch constants from the LDS header, in scalar registers: the input
+    // list, the listing threshold and the input entries to deal out
+    const uint32_t hb = hot ? (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_hot[3]) : 0u;
+    const uint32_t hthr = hot ? (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_hot[4]) : 0u;
+    const uint32_t hin = hot ? (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_hot[5]) : 0u;
 
     auto record_hit = [&](float t, uint32_t id, uint32_t f, int axis) {
         const uint32_t inst = lds_frames[f].inst;
@@ -594,12 +637,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (hot && nidle == 64u && cur_tile != 0xFFFFFFFFu) {
             // the wave's tile is done (whole tiles): listed when its slowest
-            // ray took at least the threshold's walk loop iterations
-            uint32_t m = work;
-            for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-            if (m >= hot_thr(hot) && lane == 0u) {
+            // ray took at least the threshold's advances
+            const uint32_t m = wave_max(steps);
+            tc_sum += min(m, kHotCostClamp);
+            tc_max = max(tc_max, min(m, kHotCostClamp));
+            if (m >= hthr && lane == 0u) {
                 const uint32_t i = atomicAdd(lds_hot, 1u);
-                if (i < kHotPerBlock) lds_hot[1 + i] = cur_tile;
+                if (i < kHotPerBlock) lds_hot[kHotLdsHdr + i] = cur_tile;
             }
             cur_tile = 0xFFFFFFFFu;
         }
@@ -607,12 +651,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         if (!exhausted && nidle >= refill) {
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)idle) - 1u;
             bool retrace = false;
-            if (hot) work = 0;  // lanes left without a ray in the next tile count nothing
+            if (hot) steps = 0;  // lanes left without a ray in the next tile count nothing
             bool got_hot = false;
             uint32_t htile = 0;
             if (hot_k < hin && rlo >= rhi) {
-                got_hot = true;
-                htile = hot_list(hot, hot_in(hot))[hot_k];
+                const uint32_t sub = hot_k % kHotSub, i = hot_k / kHotSub;
+                if (i < lds_hot[6 + sub]) {
+                    got_hot = true;
+                    htile = hot_list(hot, hb)[sub * kHotSubCap + i];
+                }
                 hot_k += n_active * wpb;
             }
             if (!got_hot && rlo >= rhi) {
@@ -657,7 +704,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             const uint64_t csl = (uint64_t)(first >> 6) * kQueueParts + q;
             const uint64_t ctile = hot ? (csl * tstride) % n_tiles : 0u;
             uint32_t cword = 0;
-            if (hot && take && !got_hot && hin) cword = hot_bits(hot, hot_in(hot))[ctile >> 5];
+            if (hot && take && !got_hot && hin) cword = hot_bits(hot, hb)[ctile >> 5];
             if (mode == M_DONE) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
@@ -667,7 +714,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 if (got_hot) {
                     if (rank < take && htile < n_tiles) gidx = (uint64_t)htile * 64u + rank;
                 } else if (rank < take && slot < n_tiles) {
-                    gidx = ((slot * tstride) % n_tiles) * 64u + (j & 63u);
+                    // whole tiles (always so with slow tiles first): the
+                    // claim's tile is ctile
+                    gidx = (hot ? ctile : (slot * tstride) % n_tiles) * 64u + (j & 63u);
                 }
                 if (gidx < n_rays) {
                     if constexpr (kCount) {
@@ -733,7 +782,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     best_f = -1;
                     best_axis = 3;
                     steps = 0;
-                    work = 0;
                     bws = 0;
                     // a tile of the input list was traced by the wave it was dealt to
                     const bool dealt = !got_hot && ((cword >> (ctile & 31u)) & 1u);
@@ -772,8 +820,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 }
             }
             if (hot && take) {
-                if (got_hot) cur_tile = htile < n_tiles ? htile : 0xFFFFFFFFu;
-                else cur_tile = (csl < n_tiles && !((cword >> (ctile & 31u)) & 1u)) ? (uint32_t)ctile : 0xFFFFFFFFu;
+                // wave-uniform: kept in a scalar register
+                const uint32_t t = got_hot ? (htile < n_tiles ? htile : 0xFFFFFFFFu)
+                                           : ((csl < n_tiles && !((cword >> (ctile & 31u)) & 1u)) ? (uint32_t)ctile
+                                                                                                  : 0xFFFFFFFFu);
+                cur_tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             }
             if (a.reuse && a.retraced) {
                 const uint64_t re = __ballot(retrace);
@@ -829,7 +880,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             }
             // the hot loop: visit, descend or advance until something happens
             while (ev == EV_NONE) {
-                ++work;
                 const float ex = fmaf((float)(px + size), fr.ix, fr.bx);
                 const float ey = fmaf((float)(py + size), fr.iy, fr.by);
                 const float ez = fmaf((float)(pz + size), fr.iz, fr.bz);
@@ -1052,21 +1102,28 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         }
     }
 
+    if (hot && lane == 0u) {
+        atomicAdd(lds_hot + 1, tc_sum);
+        atomicMax(lds_hot + 2, tc_max);
+    }
     // the last work-group out resets the queue for the next launch; only
     // work-groups that may claim count (an idle one of a plan's fixed grid
     // touches no counter, and skipping its atomic spares the others a
     // same-address queue)
     __syncthreads();
-    const uint32_t hp = hot ? hot_in(hot) : 0u, ob = hp ^ 1u;
+    const uint32_t hp = hot ? lds_hot[3] : 0u, ob = hp ^ 1u;
     if (hot && active && threadIdx.x == 0) {
         // this work-group's slow tiles into the output list and its bitmap
+        const uint32_t sub = blockIdx.x % kHotSub;
+        atomicAdd(hot_sum(hot, sub), lds_hot[1]);
+        atomicMax(hot_max(hot, sub), lds_hot[2]);
         const uint32_t n = min(lds_hot[0], kHotPerBlock);
         if (n) {
-            const uint32_t base = atomicAdd(hot + 2 + ob, n);
-            uint32_t* olist = hot_list(hot, ob);
+            const uint32_t base = atomicAdd(hot_cnt(hot, ob, sub), n);
+            uint32_t* olist = hot_list(hot, ob) + sub * kHotSubCap;
             uint32_t* obits = hot_bits(hot, ob);
-            for (uint32_t i = 0; i < n && base + i < kHotCap; ++i) {
-                const uint32_t t = lds_hot[1 + i];
+            for (uint32_t i = 0; i < n && base + i < kHotSubCap; ++i) {
+                const uint32_t t = lds_hot[kHotLdsHdr + i];
                 olist[base + i] = t;
                 atomicOr(obits + (t >> 5), 1u << (t & 31u));
             }
@@ -1089,24 +1146,42 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         __syncthreads();
         if (active && lds_hot[0]) {
             // last out (every other work-group has written its list): clear
-            // the input list's bitmap words, which hold only its tiles' bits
-            const uint32_t icount = min(hot[2 + hp], kHotCap);
-            const uint32_t* ilist = hot_list(hot, hp);
+            // the input list's bitmap, the words of the tiles of the launch
+            // that wrote it
+            const uint32_t iw = (min(hot[12 + hp], kHotMaxTiles) + 31u) >> 5;
             uint32_t* ibits = hot_bits(hot, hp);
-            for (uint32_t i = threadIdx.x; i < icount; i += blockDim.x) ibits[min(ilist[i], kHotMaxTiles - 1u) >> 5] = 0u;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                // the threshold follows the target count of listed tiles
-                const uint32_t c = atomicAdd(hot + 2 + ob, 0u);
-                const uint32_t tg = a.hot_target, hthr = hot_thr(hot);
-                uint32_t nt = hthr;
-                if (c > tg + tg / 2u) nt = hthr + max(1u, hthr / 8u);
-                else if (2u * c < tg && hthr > 1u) nt = hthr - max(1u, hthr / 8u);
-                atomicExch(hot + 4 + 2 * ob, (uint32_t)a.hot_sig);
-                atomicExch(hot + 5 + 2 * ob, (uint32_t)(a.hot_sig >> 32));
-                atomicExch(hot + 2 + hp, 0u);
-                atomicExch(hot + 1, nt);
-                atomicExch(hot + 0, ob);
+            for (uint32_t i = threadIdx.x; i < iw; i += blockDim.x) ibits[i] = 0u;
+            if (threadIdx.x < 64u) {
+                // the lines' counts and cost statistics, one line per lane
+                const uint32_t k = threadIdx.x;
+                uint32_t c = 0, csum = 0, cmax = 0;
+                if (k < kHotSub) {
+                    c = atomicAdd(hot_cnt(hot, ob, k), 0u);
+                    csum = atomicExch(hot_sum(hot, k), 0u);
+                    cmax = atomicExch(hot_max(hot, k), 0u);
+                    atomicExch(hot_cnt(hot, hp, k), 0u);
+                }
+                for (int off = kHotSub / 2; off > 0; off >>= 1) {
+                    c += (uint32_t)__shfl_xor((int)c, off);
+                    csum += (uint32_t)__shfl_xor((int)csum, off);
+                    cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, off));
+                }
+                if (k == 0u) {
+                    // the threshold follows the target count of listed tiles
+                    const uint32_t tg = a.hot_target, hthr = lds_hot[4];
+                    uint32_t nt = hthr;
+                    if (c > tg + tg / 2u) nt = hthr + max(1u, hthr / 8u);
+                    else if (2u * c < tg && hthr > 1u) nt = hthr - max(1u, hthr / 8u);
+                    atomicExch(hot + 4 + 2 * ob, (uint32_t)a.hot_sig);
+                    atomicExch(hot + 5 + 2 * ob, (uint32_t)(a.hot_sig >> 32));
+                    // deal the new list out only if this launch was bound by
+                    // its slowest tiles: largest cost >= 0.7 x (sum of costs /
+                    // waves)
+                    atomicExch(hot + 10 + ob, (10ull * cmax * n_active * wpb >= 7ull * csum) ? 1u : 0u);
+                    atomicExch(hot + 12 + ob, (uint32_t)n_tiles);
+                    atomicExch(hot + 1, nt);
+                    atomicExch(hot + 0, ob);
+                }
             }
         }
     }
