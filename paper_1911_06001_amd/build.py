@@ -13,6 +13,9 @@ SOURCES = [os.path.join(HERE, "csrc", "svo_host.cpp"), os.path.join(HERE, "csrc"
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # keep hipcc from emitting packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # every atomic in the kernels is issued by one lane or to per-lane
+         # addresses: the pass that merges a wave's atomics only adds code
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
          "-Wall", "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
 
 

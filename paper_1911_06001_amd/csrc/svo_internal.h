@@ -142,14 +142,26 @@ constexpr uint32_t kHotWords = kHotHdr + 2 * kHotCap + 2 * kHotBitsWords;
 // A tile's cost enters the sum and the largest cost clamped to kHotCostClamp,
 // so that a launch's sum (at most kHotMaxTiles tiles) fits 32 bits.
 constexpr uint32_t kHotCostClamp = 4095;
-// Per work-group LDS: [0] tiles listed, [1] sum and [2] largest of its tile
-// costs, [3] the input list, [4] the threshold, [5] the input entries to deal
-// out (0: none), [6 + s] sub-list s's count; then up to kHotPerBlock listed
-// tiles from kHotLdsHdr on (more are dropped).
-constexpr uint32_t kHotLdsHdr = 16;
+// Per work-group LDS words (single-job launches): the tiles it listed, the
+// sum and the largest of its tile costs, the input entries its waves have
+// taken, the input sub-lists' counts, whether the launch keeps the state, the
+// input list, the input entries to deal out (0: none), the threshold and the
+// state's address; then up to kHotPerBlock listed tiles from kHotLdsHdr on
+// (more are dropped).
+constexpr uint32_t kHotLdsListed = 0;
+constexpr uint32_t kHotLdsSum = 1;
+constexpr uint32_t kHotLdsMax = 2;
+constexpr uint32_t kHotLdsTaken = 3;
+constexpr uint32_t kHotLdsCnt = 4;                        // kHotSub words
+constexpr uint32_t kHotLdsOn = kHotLdsCnt + kHotSub;
+constexpr uint32_t kHotLdsIn = kHotLdsOn + 1;
+constexpr uint32_t kHotLdsDeal = kHotLdsOn + 2;
+constexpr uint32_t kHotLdsThr = kHotLdsOn + 3;
+constexpr uint32_t kHotLdsPtr = kHotLdsOn + 4;            // 2 words
+constexpr uint32_t kHotLdsHdr = 20;
 constexpr size_t kHotLdsBytes = 256;
 constexpr uint32_t kHotPerBlock = kHotLdsBytes / 4 - kHotLdsHdr;
-static_assert(6 + kHotSub <= kHotLdsHdr, "slow-tile LDS header too small");
+static_assert(kHotLdsPtr + 2 <= kHotLdsHdr, "slow-tile LDS header too small");
 constexpr uint32_t kHotInitialThreshold = 64;
 
 constexpr size_t kStaticQueueBytes = ((size_t)kQueueWords * 4 + 255) & ~(size_t)255;

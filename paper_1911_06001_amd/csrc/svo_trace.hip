@@ -157,6 +157,18 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)r);
 }
 
+// The slow-tile state's address from a work-group's LDS header.
+__device__ __forceinline__ uint32_t* lds_hot_ptr(const uint32_t* lds_hot) {
+    return reinterpret_cast<uint32_t*>((uint64_t)lds_hot[kHotLdsPtr] | ((uint64_t)lds_hot[kHotLdsPtr + 1] << 32));
+}
+// A wave-uniform value in scalar registers of its own.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    return reinterpret_cast<T*>((uint64_t)uniform_u32((uint32_t)v) | ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32));
+}
+
 // The hit the walk found, checked and measured in FP64.  The walk decides
 // in FP32 which cell the ray meets first; its plane crossings carry an
 // error that grows with the coordinates (frame map, reciprocal direction,
@@ -291,7 +303,8 @@ __host__ __device__ __forceinline__ size_t cand_lane_bytes(const TraceArgs& a) {
 size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
     const size_t shared = align16((size_t)a.lds_nodes * 8) + (size_t)a.n_frames * 80 +
                           align16((size_t)a.n_cand_total * 4) + (size_t)a.n_jobs * sizeof(JobRec) +
-                          (size_t)a.n_bvh_total * sizeof(BvhNode) + (a.hot ? kHotLdsBytes : 0);
+                          (size_t)a.n_bvh_total * sizeof(BvhNode) + (a.jobs ? 0 : kHotLdsBytes) +
+                          (a.has_cam0 ? sizeof(CameraArgs) : 0);
     const size_t per_wave = cand_lane_bytes(a) * 64 + (size_t)a.stack_levels * 64 * 5 + (size_t)a.nest_levels * 64 * 16;
     return shared + per_wave * waves_per_block;
 }
@@ -328,10 +341,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     p += (size_t)a.n_jobs * sizeof(JobRec);
     BvhNode* lds_bvh = reinterpret_cast<BvhNode*>(p);
     p += (size_t)a.n_bvh_total * sizeof(BvhNode);
-    // slow tiles this work-group found: count, sum and largest of its tile
-    // costs, then up to kHotPerBlock tiles
+    // slow tiles first (single-job launches): the work-group's header and the
+    // tiles it lists
     uint32_t* lds_hot = reinterpret_cast<uint32_t*>(p);
-    if (a.hot) p += kHotLdsBytes;
+    if (kSingle) p += kHotLdsBytes;
+    // a single job's camera (read once per claim; kept in LDS rather than in
+    // scalar registers for the whole launch)
+    CameraArgs* lds_cam = reinterpret_cast<CameraArgs*>(p);
+    if (a.has_cam0) p += sizeof(CameraArgs);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     const size_t ent_bytes = cand_lane_bytes(a) * 64;
@@ -411,35 +428,45 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     } else if (threadIdx.x == 0) {
         lds_jobs[0] = a.job0;
     }
+    if (kSingle && a.has_cam0 && threadIdx.x == 0) *lds_cam = a.cam0;
     // slow tiles first: the previous launch's list is this launch's input if
     // it traced the same rays (same signature); this launch's own slow tiles
     // go to the other list.  The state's header words stay fixed until the
     // last work-group out rewrites them, so each work-group reads them once
-    // into its LDS header.
+    // into its LDS header; the main loop reads the header there and the
+    // state's pointer from the arguments, which keeps them out of its scalar
+    // registers.
     const uint64_t n_tiles = (n_rays + 63) >> 6;
-    uint32_t* hot = a.hot;
-    if (a.hdr || a.jobs || n_tiles > kHotMaxTiles) hot = nullptr;
-    if (hot && threadIdx.x < kHotLdsHdr) {
-        // one round of loads: the words of both lists, then the input's
-        const uint32_t t = threadIdx.x, b = hot_in(hot);
+    if (kSingle && threadIdx.x < kHotLdsHdr) {
+        const uint32_t* hot = a.hot;
+        const uint32_t t = threadIdx.x;
         uint32_t v = 0;
-        if (t == 3) {
-            v = b;
-        } else if (t == 4) {
-            v = hot_thr(hot);
-        } else if (t == 5) {
-            uint32_t c0 = 0, c1 = 0;
-            for (uint32_t k = 0; k < kHotSub; ++k) {
-                c0 = max(c0, *hot_cnt(hot, 0, k));
-                c1 = max(c1, *hot_cnt(hot, 1, k));
+        if (hot && !a.hdr && n_tiles <= kHotMaxTiles) {
+            // one round of loads: the words of both lists, then the input's
+            const uint32_t b = hot_in(hot);
+            if (t == kHotLdsOn) {
+                v = 1u;
+            } else if (t == kHotLdsIn) {
+                v = b;
+            } else if (t == kHotLdsThr) {
+                v = hot_thr(hot);
+            } else if (t == kHotLdsDeal) {
+                uint32_t c0 = 0, c1 = 0;
+                for (uint32_t k = 0; k < kHotSub; ++k) {
+                    c0 = max(c0, hot[kHotCntBase + k * kHotLine]);
+                    c1 = max(c1, hot[kHotCntBase + (kHotSub + k) * kHotLine]);
+                }
+                const bool d0 = hot[10] && ((uint64_t)hot[4] | ((uint64_t)hot[5] << 32)) == a.hot_sig;
+                const bool d1 = hot[11] && ((uint64_t)hot[6] | ((uint64_t)hot[7] << 32)) == a.hot_sig;
+                // entry e is sub-list e mod kHotSub's (e / kHotSub)-th
+                if (b ? d1 : d0) v = min(b ? c1 : c0, kHotSubCap) * kHotSub;
+            } else if (t >= kHotLdsCnt && t < kHotLdsCnt + kHotSub) {
+                const uint32_t k = t - kHotLdsCnt;
+                const uint32_t c0 = hot[kHotCntBase + k * kHotLine], c1 = hot[kHotCntBase + (kHotSub + k) * kHotLine];
+                v = min(b ? c1 : c0, kHotSubCap);
+            } else if (t == kHotLdsPtr || t == kHotLdsPtr + 1) {
+                v = (uint32_t)(reinterpret_cast<uint64_t>(hot) >> (t == kHotLdsPtr ? 0 : 32));
             }
-            const bool d0 = hot[10] && ((uint64_t)hot[4] | ((uint64_t)hot[5] << 32)) == a.hot_sig;
-            const bool d1 = hot[11] && ((uint64_t)hot[6] | ((uint64_t)hot[7] << 32)) == a.hot_sig;
-            // entry e is sub-list e mod kHotSub's (e / kHotSub)-th
-            if (b ? d1 : d0) v = min(b ? c1 : c0, kHotSubCap) * kHotSub;
-        } else if (t >= 6 && t < 6 + kHotSub) {
-            const uint32_t c0 = *hot_cnt(hot, 0, t - 6), c1 = *hot_cnt(hot, 1, t - 6);
-            v = min(b ? c1 : c0, kHotSubCap);
         }
         lds_hot[t] = v;
     }
@@ -458,10 +485,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     uint32_t ri = 0;           // ray index within its job (a launch holds at most 0xff000000 rays)
     uint32_t gray = 0, c_nodes = 0, c_frames = 0, c_trail = 0;   // counting build only
     uint32_t job = 0;
-    const uint64_t* nodes = kSingle ? a.job0.nodes : nullptr;
-    uint32_t n_lds = kSingle ? min(a.job0.lds_nodes, fill_nodes) : 0u;
-    uint32_t fbase = kSingle ? a.job0.frame_base : 0u, cbase = kSingle ? a.job0.cand_base : 0u;
-    uint32_t ncand = kSingle ? a.job0.n_cand : 0u;
+    // a single job's constants come from its LDS copy, made wave-uniform:
+    // read from the arguments, they would share one wide scalar load with
+    // fields the loop never uses, and be kept or spilled with them
+    const uint64_t* nodes = kSingle ? uniform_ptr(lds_jobs[0].nodes) : nullptr;
+    uint32_t n_lds = kSingle ? min(uniform_u32(lds_jobs[0].lds_nodes), fill_nodes) : 0u;
+    uint32_t fbase = kSingle ? uniform_u32(lds_jobs[0].frame_base) : 0u;
+    uint32_t cbase = kSingle ? uniform_u32(lds_jobs[0].cand_base) : 0u;
+    uint32_t ncand = kSingle ? uniform_u32(lds_jobs[0].n_cand) : 0u;
     Ray r{};
     float best_t = INFINITY, tl = 0.f;
     uint32_t best_id = kNone, best_inst = kNone;
@@ -487,17 +518,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
     // is itself a solid leaf (recorded where every walk hit is)
     uint32_t pend = 0;
     bool exhausted = !active;  // wave-uniform
-    // slow tiles first (wave-uniform): the next input entry this wave takes
-    // (entries are dealt out over the active waves), and the tile its lanes
-    // are tracing (whole-tile refill)
-    uint32_t hot_k = blockIdx.x * wpb + wave;
+    // slow tiles first: the tile the wave's lanes are tracing (whole-tile
+    // refill; set only while the launch keeps the slow-tile state)
     uint32_t cur_tile = 0xFFFFFFFFu;
-    uint32_t tc_sum = 0, tc_max = 0;   // the wave's tile costs (clamped)
-    // launch constants from the LDS header, in scalar registers: the input
-    // list, the listing threshold and the input entries to deal out
-    const uint32_t hb = hot ? (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_hot[3]) : 0u;
-    const uint32_t hthr = hot ? (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_hot[4]) : 0u;
-    const uint32_t hin = hot ? (uint32_t)__builtin_amdgcn_readfirstlane((int)lds_hot[5]) : 0u;
 
     auto record_hit = [&](float t, uint32_t id, uint32_t f, int axis) {
         const uint32_t inst = lds_frames[f].inst;
@@ -635,15 +658,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         // ---------------------------------------------------------- refill
         const uint64_t idle = __ballot(mode == M_DONE);
         const uint32_t nidle = (uint32_t)__popcll(idle);
-        if (hot && nidle == 64u && cur_tile != 0xFFFFFFFFu) {
+        if (nidle == 64u && cur_tile != 0xFFFFFFFFu) {
             // the wave's tile is done (whole tiles): listed when its slowest
             // ray took at least the threshold's advances
             const uint32_t m = wave_max(steps);
-            tc_sum += min(m, kHotCostClamp);
-            tc_max = max(tc_max, min(m, kHotCostClamp));
-            if (m >= hthr && lane == 0u) {
-                const uint32_t i = atomicAdd(lds_hot, 1u);
-                if (i < kHotPerBlock) lds_hot[kHotLdsHdr + i] = cur_tile;
+            steps = 0;   // lanes left without a ray in the next tile count nothing
+            if (lane == 0u) {
+                atomicAdd(lds_hot + kHotLdsSum, min(m, kHotCostClamp));
+                atomicMax(lds_hot + kHotLdsMax, min(m, kHotCostClamp));
+                if (m >= lds_hot[kHotLdsThr]) {
+                    const uint32_t i = atomicAdd(lds_hot + kHotLdsListed, 1u);
+                    if (i < kHotPerBlock) lds_hot[kHotLdsHdr + i] = cur_tile;
+                }
             }
             cur_tile = 0xFFFFFFFFu;
         }
@@ -651,16 +677,29 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         if (!exhausted && nidle >= refill) {
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)idle) - 1u;
             bool retrace = false;
-            if (hot) steps = 0;  // lanes left without a ray in the next tile count nothing
+            // slow tiles first: whether this launch keeps the state, and
+            // the input entries to deal out
             bool got_hot = false;
-            uint32_t htile = 0;
-            if (hot_k < hin && rlo >= rhi) {
-                const uint32_t sub = hot_k % kHotSub, i = hot_k / kHotSub;
-                if (i < lds_hot[6 + sub]) {
+            uint32_t htile = 0, hon = 0, hin = 0;
+            if constexpr (kSingle) {
+                hon = lds_hot[kHotLdsOn];
+                hin = lds_hot[kHotLdsDeal];
+            }
+            if (hin && rlo >= rhi) {
+                // the work-group's next entry, claimed by the leader for the
+                // wave (hin and the counts stay fixed during the launch):
+                // its k-th claim takes entry (k / wpb) W + blockIdx.x wpb +
+                // k mod wpb, W = n_active wpb, so that the first W entries
+                // go one to each wave of the grid in work-group order
+                uint32_t k = 0;
+                if (lane == leader) k = atomicAdd(lds_hot + kHotLdsTaken, 1u);
+                k = (uint32_t)__shfl((int)k, (int)leader);
+                const uint64_t e = (uint64_t)(k / wpb) * n_active * wpb + (uint64_t)blockIdx.x * wpb + k % wpb;
+                const uint32_t sub = (uint32_t)(e % kHotSub), i = (uint32_t)(e / kHotSub);
+                if (e < hin && i < lds_hot[kHotLdsCnt + sub]) {
                     got_hot = true;
-                    htile = hot_list(hot, hb)[sub * kHotSubCap + i];
+                    htile = hot_list(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn])[sub * kHotSubCap + i];
                 }
-                hot_k += n_active * wpb;
             }
             if (!got_hot && rlo >= rhi) {
                 // claim the next range of partition q.  A dry partition is
@@ -702,9 +741,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             // and the input bitmap's word for it, tested once the rays'
             // loads are on their way
             const uint64_t csl = (uint64_t)(first >> 6) * kQueueParts + q;
-            const uint64_t ctile = hot ? (csl * tstride) % n_tiles : 0u;
+            const uint64_t ctile = (csl * tstride) % n_tiles;
             uint32_t cword = 0;
-            if (hot && take && !got_hot && hin) cword = hot_bits(hot, hb)[ctile >> 5];
+            if (take && !got_hot && hin) cword = hot_bits(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn])[ctile >> 5];
             if (mode == M_DONE) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
@@ -714,9 +753,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 if (got_hot) {
                     if (rank < take && htile < n_tiles) gidx = (uint64_t)htile * 64u + rank;
                 } else if (rank < take && slot < n_tiles) {
-                    // whole tiles (always so with slow tiles first): the
-                    // claim's tile is ctile
-                    gidx = (hot ? ctile : (slot * tstride) % n_tiles) * 64u + (j & 63u);
+                    // a lane in the claim's first tile (every lane, with
+                    // whole tiles) takes its tile from ctile
+                    gidx = ((j >> 6) == (first >> 6) ? ctile : (slot * tstride) % n_tiles) * 64u + (j & 63u);
                 }
                 if (gidx < n_rays) {
                     if constexpr (kCount) {
@@ -726,8 +765,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     const float4* rays;
                     const CameraArgs* cam = nullptr;
                     if constexpr (kSingle) {
-                        ri = (uint32_t)(gidx - a.job0.ray_begin);
-                        rays = a.job0.rays;
+                        ri = (uint32_t)(gidx - lds_jobs[0].ray_begin);
+                        rays = lds_jobs[0].rays;
                     } else {
                         // the job holding this launch-wide ray index (jobs are in ray order)
                         uint32_t lo = 0, hi = n_jobs;
@@ -752,8 +791,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     bool made = false;
                     if constexpr (kSingle) {
                         if (a.has_cam0) {
+                            uint32_t w[sizeof(CameraArgs) / 4];
+                            const uint32_t* src = reinterpret_cast<const uint32_t*>(lds_cam);
+                            for (int k = 0; k < (int)(sizeof(CameraArgs) / 4); ++k) w[k] = uniform_u32(src[k]);
+                            CameraArgs C;
+                            std::memcpy(&C, w, sizeof C);
                             float4 c0, c1;
-                            camera_ray(a.cam0, ri, c0, c1);
+                            camera_ray(C, ri, c0, c1);
                             r = Ray{c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
                             made = true;
                         }
@@ -819,8 +863,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     }
                 }
             }
-            if (hot && take) {
-                // wave-uniform: kept in a scalar register
+            if (hon && take) {
+                // wave-uniform
                 const uint32_t t = got_hot ? (htile < n_tiles ? htile : 0xFFFFFFFFu)
                                            : ((csl < n_tiles && !((cword >> (ctile & 31u)) & 1u)) ? (uint32_t)ctile
                                                                                                   : 0xFFFFFFFFu);
@@ -1102,22 +1146,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
         }
     }
 
-    if (hot && lane == 0u) {
-        atomicAdd(lds_hot + 1, tc_sum);
-        atomicMax(lds_hot + 2, tc_max);
-    }
     // the last work-group out resets the queue for the next launch; only
     // work-groups that may claim count (an idle one of a plan's fixed grid
     // touches no counter, and skipping its atomic spares the others a
     // same-address queue)
     __syncthreads();
-    const uint32_t hp = hot ? lds_hot[3] : 0u, ob = hp ^ 1u;
+    uint32_t* const hot = (kSingle && lds_hot[kHotLdsOn]) ? a.hot : nullptr;
+    const uint32_t hp = hot ? lds_hot[kHotLdsIn] : 0u, ob = hp ^ 1u;
     if (hot && active && threadIdx.x == 0) {
         // this work-group's slow tiles into the output list and its bitmap
         const uint32_t sub = blockIdx.x % kHotSub;
-        atomicAdd(hot_sum(hot, sub), lds_hot[1]);
-        atomicMax(hot_max(hot, sub), lds_hot[2]);
-        const uint32_t n = min(lds_hot[0], kHotPerBlock);
+        atomicAdd(hot_sum(hot, sub), lds_hot[kHotLdsSum]);
+        atomicMax(hot_max(hot, sub), lds_hot[kHotLdsMax]);
+        const uint32_t n = min(lds_hot[kHotLdsListed], kHotPerBlock);
         if (n) {
             const uint32_t base = atomicAdd(hot_cnt(hot, ob, sub), n);
             uint32_t* olist = hot_list(hot, ob) + sub * kHotSubCap;
@@ -1140,11 +1181,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             atomicExch(a.queue + kQueueDry + 1, 0u);
             atomicExch(fin, 0u);
         }
-        if (hot) lds_hot[0] = last ? 1u : 0u;
+        if (hot) lds_hot[kHotLdsListed] = last ? 1u : 0u;
     }
     if (hot) {
         __syncthreads();
-        if (active && lds_hot[0]) {
+        if (active && lds_hot[kHotLdsListed]) {
             // last out (every other work-group has written its list): clear
             // the input list's bitmap, the words of the tiles of the launch
             // that wrote it
@@ -1168,7 +1209,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 }
                 if (k == 0u) {
                     // the threshold follows the target count of listed tiles
-                    const uint32_t tg = a.hot_target, hthr = lds_hot[4];
+                    const uint32_t tg = a.hot_target, hthr = lds_hot[kHotLdsThr];
                     uint32_t nt = hthr;
                     if (c > tg + tg / 2u) nt = hthr + max(1u, hthr / 8u);
                     else if (2u * c < tg && hthr > 1u) nt = hthr - max(1u, hthr / 8u);
