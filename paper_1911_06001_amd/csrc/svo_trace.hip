@@ -316,7 +316,7 @@ size_t trace_lds_bytes(const TraceArgs& a, uint32_t waves_per_block) {
 // for 6 resident waves per SIMD (80 VGPRs): the few values that then go to
 // scratch are per-ray state outside the walk loop, and the extra waves hide
 // more of the node-load latency.  The hierarchy one keeps its natural
-// count (93 VGPRs single-job, 101 batched): forcing it lower spills inside
+// count (102 VGPRs single-job, 110 batched): forcing it lower spills inside
 // its candidate search.
 // kSingle: a one-job launch (the job in the arguments), whose pool, cache
 // size and table offsets are then launch-wide values (scalar registers)
