@@ -131,11 +131,12 @@ typedef struct {
                                    through the box hierarchy over their world boxes (a scene whose table travels
                                    in the kernel arguments always takes the sorted table) */
     uint32_t tile_order;        /* 0: slow tiles first, 1: the plain claim order.  With 0, a one-job trace with
-                                   whole-tile claims (refill_lanes 0 or 64) lists the 64-ray tiles whose
-                                   slowest ray took the most walk steps (about the slowest 4 %) in its work
-                                   queue's state, and the next trace of the same rays on the same stream hands
-                                   those tiles to its waves first, so that the launch's longest chains start at
-                                   its beginning instead of setting its end.  Order only: results are the same. */
+                                   whole-tile claims (refill_lanes 0 or 64; not the hit buffer) lists the 64-ray
+                                   tiles whose slowest ray took the most walk steps (about the slowest 12 %) in
+                                   its work queue's state, and the next trace of the same rays on the same
+                                   stream hands those tiles to its waves first, so that the launch's longest
+                                   chains start at its beginning instead of setting its end.  Order only:
+                                   results are the same. */
 } svo_config;
 
 /* ABI version the library was built with (SVO_ABI_VERSION). */

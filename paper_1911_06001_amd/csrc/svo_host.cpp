@@ -1324,9 +1324,11 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
         a.cam0 = *cam;
     }
     // slow tiles first (whole-tile claims): the queue's state carries them
-    // from the previous launch of the same rays
+    // from the previous launch of the same rays.  Hit-buffer launches keep
+    // the plain order: the few rays they trace again change from frame to
+    // frame, so the previous launch's slow tiles say little about theirs.
     const uint64_t tiles = (n + 63) / 64;
-    if (cfg.tile_order == 0 && a.refill == 64 && tiles <= svo::kHotMaxTiles) {
+    if (cfg.tile_order == 0 && a.refill == 64 && !reuse && tiles <= svo::kHotMaxTiles) {
         const uint64_t sig = ray_signature(scene, rays, n, cam);
         auto& R = ctx->hot_rec[qslot];
         uint32_t k = R.sig[0] == sig ? 0u : (R.sig[1] == sig ? 1u : 2u);
@@ -1339,7 +1341,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
         if (R.uses[k] < 2u) ++R.uses[k];
         if (R.uses[k] >= 2u) {
             a.hot = ctx->d_hot + (size_t)svo::kHotWords * (2u * qslot + k);
-            a.hot_target = (uint32_t)std::min<uint64_t>(svo::kHotCap, std::max<uint64_t>(16, tiles / 25));
+            a.hot_target = (uint32_t)std::min<uint64_t>(svo::kHotCap, std::max<uint64_t>(16, tiles / 8));
             a.hot_sig = sig;
         }
     }

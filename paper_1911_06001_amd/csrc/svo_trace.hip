@@ -698,8 +698,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 const uint32_t sub = (uint32_t)(e % kHotSub), i = (uint32_t)(e / kHotSub);
                 if (e < hin && i < lds_hot[kHotLdsCnt + sub]) {
                     got_hot = true;
-                    htile = hot_list(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn])[sub * kHotSubCap + i];
+                    htile = gld(hot_list(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn]), (uint64_t)sub * kHotSubCap + i);
                 }
+            }
+            if constexpr (kSorted) {
+                // a dealt tile was among the previous launch's slowest: its
+                // wave issues ahead of the others on its SIMD while it runs
+                // (a scalar branch: s_setprio ignores the lane mask)
+                if (uniform_u32(got_hot ? 1u : 0u)) __builtin_amdgcn_s_setprio(3);
+                else __builtin_amdgcn_s_setprio(0);
             }
             if (!got_hot && rlo >= rhi) {
                 // claim the next range of partition q.  A dry partition is
@@ -743,7 +750,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             const uint64_t csl = (uint64_t)(first >> 6) * kQueueParts + q;
             const uint64_t ctile = (csl * tstride) % n_tiles;
             uint32_t cword = 0;
-            if (take && !got_hot && hin) cword = hot_bits(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn])[ctile >> 5];
+            if (take && !got_hot && hin) cword = gld(hot_bits(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn]), ctile >> 5);
             if (mode == M_DONE) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
