@@ -126,13 +126,21 @@ constexpr uint32_t kQueueWords = kQueueFinished + kQueueStride;
 // launch that wrote it; then per line s: list b's count (raw, may pass
 // kHotSubCap) at hot_cnt(b, s), this launch's sum and largest of tile costs
 // at hot_sum(s) and hot_max(s); then list 0, list 1 (kHotSub sub-lists of
-// kHotSubCap tile indices each), bitmap 0, bitmap 1 (a bit per tile of the
-// launch that wrote it).
+// kHotSubCap entries each), bitmap 0, bitmap 1 (a bit per tile of the launch
+// that wrote it).
 constexpr uint32_t kHotSub = 8;
 constexpr uint32_t kHotLine = 32;                // words per cache line (128 B)
 constexpr uint32_t kHotSubCap = 1024;
 constexpr uint32_t kHotCap = kHotSub * kHotSubCap;
-constexpr uint32_t kHotMaxTiles = 1u << 18;      // launches with more tiles keep the plain order
+constexpr uint32_t kHotTileBits = 18;
+constexpr uint32_t kHotMaxTiles = 1u << kHotTileBits;   // launches with more tiles keep the plain order
+// A list entry is a tile index in its low kHotTileBits bits and the tile's
+// cost, clamped, above them.
+constexpr uint32_t kHotTileMask = kHotMaxTiles - 1u;
+constexpr uint32_t kHotEntryCostMax = (1u << (32 - kHotTileBits)) - 1u;
+// The sorted instantiation raises the issue priority of a wave on a dealt
+// tile whose cost is at least this many tenths of the listing threshold.
+constexpr uint32_t kHotPrioTenths = 20;
 constexpr uint32_t kHotBitsWords = kHotMaxTiles / 32;
 constexpr uint32_t kHotCntBase = kHotLine;                                  // 2 kHotSub lines
 constexpr uint32_t kHotSumBase = kHotCntBase + 2 * kHotSub * kHotLine;      // kHotSub lines

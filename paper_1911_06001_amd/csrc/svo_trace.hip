@@ -668,7 +668,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 atomicMax(lds_hot + kHotLdsMax, min(m, kHotCostClamp));
                 if (m >= lds_hot[kHotLdsThr]) {
                     const uint32_t i = atomicAdd(lds_hot + kHotLdsListed, 1u);
-                    if (i < kHotPerBlock) lds_hot[kHotLdsHdr + i] = cur_tile;
+                    if (i < kHotPerBlock) lds_hot[kHotLdsHdr + i] = cur_tile | (min(m, kHotEntryCostMax) << kHotTileBits);
                 }
             }
             cur_tile = 0xFFFFFFFFu;
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             // slow tiles first: whether this launch keeps the state, and
             // the input entries to deal out
             bool got_hot = false;
-            uint32_t htile = 0, hon = 0, hin = 0;
+            uint32_t htile = 0, hcost = 0, hon = 0, hin = 0;
             if constexpr (kSingle) {
                 hon = lds_hot[kHotLdsOn];
                 hin = lds_hot[kHotLdsDeal];
@@ -698,14 +698,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                 const uint32_t sub = (uint32_t)(e % kHotSub), i = (uint32_t)(e / kHotSub);
                 if (e < hin && i < lds_hot[kHotLdsCnt + sub]) {
                     got_hot = true;
-                    htile = gld(hot_list(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn]), (uint64_t)sub * kHotSubCap + i);
+                    const uint32_t ent = gld(hot_list(lds_hot_ptr(lds_hot), lds_hot[kHotLdsIn]), (uint64_t)sub * kHotSubCap + i);
+                    htile = ent & kHotTileMask;
+                    hcost = ent >> kHotTileBits;
                 }
             }
             if constexpr (kSorted) {
-                // a dealt tile was among the previous launch's slowest: its
+                // a dealt tile among the previous launch's costliest: its
                 // wave issues ahead of the others on its SIMD while it runs
                 // (a scalar branch: s_setprio ignores the lane mask)
-                if (uniform_u32(got_hot ? 1u : 0u)) __builtin_amdgcn_s_setprio(3);
+                const bool up = got_hot && 10ull * hcost >= (uint64_t)kHotPrioTenths * lds_hot[kHotLdsThr];
+                if (uniform_u32(up ? 1u : 0u)) __builtin_amdgcn_s_setprio(3);
                 else __builtin_amdgcn_s_setprio(0);
             }
             if (!got_hot && rlo >= rhi) {
@@ -1171,8 +1174,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             uint32_t* olist = hot_list(hot, ob) + sub * kHotSubCap;
             uint32_t* obits = hot_bits(hot, ob);
             for (uint32_t i = 0; i < n && base + i < kHotSubCap; ++i) {
-                const uint32_t t = lds_hot[kHotLdsHdr + i];
-                olist[base + i] = t;
+                const uint32_t ent = lds_hot[kHotLdsHdr + i], t = ent & kHotTileMask;
+                olist[base + i] = ent;
                 atomicOr(obits + (t >> 5), 1u << (t & 31u));
             }
         }
