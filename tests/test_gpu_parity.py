@@ -679,6 +679,53 @@ def test_hierarchy_over_many_candidates(ctx, torch_dev, n_slots):
         ctx.free_scene(hs)
 
 
+def test_slow_tiles_first_hierarchy_and_camera(ctx, torch_dev):
+    """Slow tiles first in the other single-job instantiations: the
+    candidate hierarchy (more than 16 candidate frames, which keeps the plain
+    issue priority) and the camera trace (rays made in the kernel from the
+    camera record kept in LDS; its ray set is named by the camera).  Each ray
+    set on its own (a queue keeps two sets' lists), traced repeatedly with
+    the transforms changing between traces: tile_order 0 equals tile_order 1
+    bit for bit."""
+    torch = torch_dev
+    from paper_1911_06001_amd import svo
+    sc = S.tiny_scene(11, K=7, n_slots=60, nested=False, scale_range=(0.8, 2.0), translate=0.3)
+    rays = torch.from_numpy(np.concatenate([S.random_rays(3, 20000, -40.0, 168.0),
+                                            S.random_rays(4, 6000, 20.0, 108.0)])).cuda()
+    ter = S.fbm_terrain_d10()
+    h = ctx.upload_scene(sc)
+    ht = ctx.upload_scene(ter)
+    c = ter.camera
+    cams = [svo.make_camera(c["eye"], c["target"], c["up"], c["fov"], 320, 184),
+            svo.make_camera(c["eye"], c["target"], c["up"], c["fov"], 96, 40, samples=2, seed=5, jitter=True)]
+    cases = [("hierarchy", h, sc, lambda: ctx.trace(h, rays))] + \
+        [("camera%d" % i, ht, ter, (lambda cm: (lambda: ctx.trace_camera(ht, cm)))(cm)) for i, cm in enumerate(cams)]
+    base_cfg = ctx.get_config().as_dict()
+    try:
+        ctx.set_transforms(h, sc.xform(0))
+        assert ctx.scene_stats(h).n_candidates > 16
+        frames = (0, 9, 18)
+        for label, sh, scene, run in cases:
+            ctx.set_config(waves_per_block=4, blocks_per_cu=2, lds_cache_nodes=1024, refill_lanes=0, tile_order=1)
+            ref = {}
+            for f in frames:
+                ctx.set_transforms(sh, scene.xform(f))
+                ref[f] = run()
+            ctx.set_config(tile_order=0)
+            for rep in range(3):
+                for f in frames:
+                    ctx.set_transforms(sh, scene.xform(f))
+                    o = run()
+                    torch.cuda.synchronize()
+                    e = ref[f]
+                    assert torch.equal(o.id, e.id) and torch.equal(o.inst, e.inst), (label, rep, f)
+                    assert torch.equal(o.t, e.t) and torch.equal(o.normal, e.normal), (label, rep, f)
+    finally:
+        ctx.set_config(**base_cfg)
+        ctx.free_scene(h)
+        ctx.free_scene(ht)
+
+
 def test_slow_tiles_first_keeps_results(ctx, torch_dev):
     """tile_order 0 hands the tiles that were slowest in the previous trace of
     the same rays (on the same stream) to the waves first; tile_order 1 keeps
