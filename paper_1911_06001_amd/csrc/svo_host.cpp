@@ -331,6 +331,7 @@ struct svo_ctx {
     struct HotRec {
         uint64_t sig[2] = {0, 0};
         uint32_t uses[2] = {0, 0};
+        uint32_t seq[2] = {0, 0};   // launches on each state
         uint32_t recent = 0;    // the state used last (the other one is replaced first)
     };
     HotRec hot_rec[kMaxStreams];
@@ -1342,6 +1343,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
         if (R.uses[k] >= 2u) {
             a.hot = ctx->d_hot + (size_t)svo::kHotWords * (2u * qslot + k);
             a.hot_target = (uint32_t)std::min<uint64_t>(svo::kHotCap, std::max<uint64_t>(16, tiles / 8));
+            a.hot_seq = R.seq[k]++;
             a.hot_sig = sig;
         }
     }

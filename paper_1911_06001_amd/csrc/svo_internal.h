@@ -141,6 +141,10 @@ constexpr uint32_t kHotEntryCostMax = (1u << (32 - kHotTileBits)) - 1u;
 // The sorted instantiation raises the issue priority of a wave on a dealt
 // tile whose cost is at least this many tenths of the listing threshold.
 constexpr uint32_t kHotPrioTenths = 20;
+// A launch whose input list is of its own rays but was not to be dealt out
+// gathers no tile statistics (and leaves the state as it is), except every
+// kHotResample-th launch on the state, which decides again.
+constexpr uint32_t kHotResample = 8;
 constexpr uint32_t kHotBitsWords = kHotMaxTiles / 32;
 constexpr uint32_t kHotCntBase = kHotLine;                                  // 2 kHotSub lines
 constexpr uint32_t kHotSumBase = kHotCntBase + 2 * kHotSub * kHotLine;      // kHotSub lines
@@ -241,6 +245,7 @@ struct TraceArgs {
     // listed tiles, and the signature of this launch's rays
     uint32_t* hot;
     uint32_t hot_target;
+    uint32_t hot_seq;         // launches so far on this state (see kHotResample)
     uint64_t hot_sig;
     // TraceArgsInline launches: frames, cand, spheres and exact maps are read
     // from the inline table at these byte offsets instead of the pointers above

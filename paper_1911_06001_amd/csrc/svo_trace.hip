@@ -445,7 +445,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
             // one round of loads: the words of both lists, then the input's
             const uint32_t b = hot_in(hot);
             if (t == kHotLdsOn) {
-                v = 1u;
+                const bool same = ((uint64_t)hot[4 + 2 * b] | ((uint64_t)hot[5 + 2 * b] << 32)) == a.hot_sig;
+                v = (!same || hot[10 + b] || a.hot_seq % kHotResample == 0) ? 1u : 0u;
             } else if (t == kHotLdsIn) {
                 v = b;
             } else if (t == kHotLdsThr) {
