@@ -331,7 +331,8 @@ struct svo_ctx {
     struct HotRec {
         uint64_t sig[2] = {0, 0};
         uint32_t uses[2] = {0, 0};
-        uint32_t seq[2] = {0, 0};   // launches on each state
+        uint32_t seq[2] = {0, 0};   // launches on each state since its launch shape last changed
+        uint32_t shape[2] = {0, 0}; // that shape (waves per work-group, work-groups per CU)
         uint32_t recent = 0;    // the state used last (the other one is replaced first)
     };
     HotRec hot_rec[kMaxStreams];
@@ -1341,6 +1342,14 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
         R.recent = k;
         if (R.uses[k] < 2u) ++R.uses[k];
         if (R.uses[k] >= 2u) {
+            // whether a list is dealt out depends on the waves of the launch
+            // that wrote it: a new shape starts a new count, so that its first
+            // launch gathers statistics and decides for that shape
+            const uint32_t shape = (cfg.waves_per_block << 16) | cfg.blocks_per_cu;
+            if (R.shape[k] != shape) {
+                R.shape[k] = shape;
+                R.seq[k] = 0;
+            }
             a.hot = ctx->d_hot + (size_t)svo::kHotWords * (2u * qslot + k);
             a.hot_target = (uint32_t)std::min<uint64_t>(svo::kHotCap, std::max<uint64_t>(16, tiles / 8));
             a.hot_seq = R.seq[k]++;
