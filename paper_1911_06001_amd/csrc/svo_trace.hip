@@ -29,12 +29,19 @@
 // and refills lanes once `refill` of them are idle (64 = whole tiles), from
 // a range of `claim` rays it takes at once from one of kQueueParts counters
 // (claims interleaved over the counters, each wave starting on its own), so
-// that no single address serialises the claims.  Claims visit
-// the 64-ray tiles in a stride permutation, so that expensive regions of an
-// image (rays grazing a surface) spread over time and over waves instead of
-// reaching a few waves back to back.  The last
-// work-group to finish resets the counters so the next launch on the stream
-// starts from zero.
+// that no single address serialises the claims.  Claims visit the 64-ray
+// tiles in a stride permutation, so that expensive regions of an image (rays
+// grazing a surface) spread over time and over waves instead of reaching a
+// few waves back to back.  The last work-group to finish resets the counters
+// so the next launch on the stream starts from zero.
+//
+// Slow tiles first (one-job launches with whole tiles): a launch ends when
+// its longest chains of walk steps do, and the same rays traced again (an
+// animation under a fixed camera) have their costliest tiles in nearly the
+// same places.  Each launch lists the tiles whose longest ray took the most
+// advances in its work queue's state (kHot*), and the next launch on the same
+// rays deals those tiles to its waves before any regular claim, while the
+// regular order skips them; results never depend on the order.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
