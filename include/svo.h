@@ -430,8 +430,8 @@ int svo_set_config(svo_ctx* ctx, const svo_config* cfg);
    against `scene` under its current transforms, in two stages: the launch
    shape (waves per work-group, work-groups per CU, LDS pool-prefix size),
    then lane refill, tiles per work-queue claim and the candidate ordering
-   (sorted table or hierarchy) for the fastest shape, then five times longer timings of that winner and the next
-   two shapes.  Infrastructure: no passage of the paper defines it.  Keeps
+   (sorted table or hierarchy) for the fastest shape, then five times longer timings of that winner, the first
+   stage's winner and the next two shapes.  Infrastructure: no passage of the paper defines it.  Keeps
    the fastest for that scene -- later svo_trace_rays calls on it use it, and
    a batch uses it when that scene holds most of the batch's rays -- and
    writes it to *best (nullable).  Results never depend on the

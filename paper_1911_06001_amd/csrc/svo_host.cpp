@@ -1835,6 +1835,7 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
             }
         }
     try_all(cands, true);
+    const svo_config shape1 = win;   // the first stage's winner
     if (rc == SVO_OK || rc == SVO_ERANGE) {
         const svo_config shape = win;
         cands.clear();
@@ -1856,15 +1857,19 @@ int svo_tune(svo_ctx* ctx, svo_scene scene, const float* sample_rays, uint64_t n
         }
         try_all(cands, false);
     }
-    // Short timings are noisy: the winner and the next two shapes of the
-    // first stage are timed again with five times the launches, and the
-    // fastest of them is kept.
+    // Short timings are noisy: the winner, the first stage's winner (when the
+    // second stage changed it) and the next two shapes of the first stage are
+    // timed again with five times the launches, and the fastest is kept.
     if ((rc == SVO_OK || rc == SVO_ERANGE) && win_ms < 1e30f) {
         std::sort(shapes.begin(), shapes.end(), [](const std::pair<float, svo_config>& x,
                                                    const std::pair<float, svo_config>& y) { return x.first < y.first; });
         std::vector<svo_config> finalists{win};
-        for (size_t i = 0; i < shapes.size() && finalists.size() < 3; ++i)
-            if (std::memcmp(&shapes[i].second, &win, sizeof win) != 0) finalists.push_back(shapes[i].second);
+        if (std::memcmp(&shape1, &win, sizeof win) != 0) finalists.push_back(shape1);
+        const size_t n_final = finalists.size() + 2;
+        for (size_t i = 0; i < shapes.size() && finalists.size() < n_final; ++i)
+            if (std::memcmp(&shapes[i].second, &win, sizeof win) != 0 &&
+                std::memcmp(&shapes[i].second, &shape1, sizeof shape1) != 0)
+                finalists.push_back(shapes[i].second);
         float best_ms = 1e30f;
         for (const svo_config& cand : finalists) {
             float ms = 0.f;
