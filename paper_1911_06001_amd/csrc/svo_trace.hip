@@ -711,7 +711,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kSorted ? 
                     hcost = ent >> kHotTileBits;
                 }
             }
-            if constexpr (kSorted) {
+            if constexpr (kSorted && kSingle) {
                 // a dealt tile among the previous launch's costliest: its
                 // wave issues ahead of the others on its SIMD while it runs
                 // (a scalar branch: s_setprio ignores the lane mask)
