@@ -333,6 +333,7 @@ struct svo_ctx {
         uint32_t uses[2] = {0, 0};
         uint32_t seq[2] = {0, 0};   // launches on each state since its launch shape last changed
         uint32_t shape[2] = {0, 0}; // that shape (waves per work-group, work-groups per CU)
+        bool fresh[2] = {false, false};  // handed to a new ray set: its threshold starts again
         uint32_t recent = 0;    // the state used last (the other one is replaced first)
     };
     HotRec hot_rec[kMaxStreams];
@@ -1338,6 +1339,7 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
             k = R.recent ^ 1u;
             R.sig[k] = sig;
             R.uses[k] = 0;
+            R.fresh[k] = true;
         }
         R.recent = k;
         if (R.uses[k] < 2u) ++R.uses[k];
@@ -1351,6 +1353,14 @@ int trace_rays(svo_ctx* ctx, svo_scene scene, const float* rays, uint64_t n, uin
                 R.seq[k] = 0;
             }
             a.hot = ctx->d_hot + (size_t)svo::kHotWords * (2u * qslot + k);
+            if (R.fresh[k]) {
+                // the listing threshold was the previous ray set's: start from
+                // the initial one (a fill kernel rather than a memset, so that
+                // the trace can be captured in a graph)
+                R.fresh[k] = false;
+                if (svo::launch_zero_words(a.hot + 1, 1, st) != hipSuccess)
+                    return fail(SVO_EDEVICE, "slow-tile state reset failed");
+            }
             a.hot_target = (uint32_t)std::min<uint64_t>(svo::kHotCap, std::max<uint64_t>(16, tiles / 8));
             a.hot_seq = R.seq[k]++;
             a.hot_sig = sig;
